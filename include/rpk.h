@@ -1,0 +1,157 @@
+/*
+ * rpk.h -- C ABI of the reproducible (exactly rounded) PBiCGStab library for MI355X.
+ *
+ * The operations are those of Iakymchuk & Aliaga, "General framework for
+ * re-assuring numerical reliability in parallel Krylov solvers: A case of BiCGStab
+ * methods":
+ *   - exdot: the dot product, correctly rounded (nearest, ties to even) from the
+ *     exact real value (Sec. 2, ExBLAS exdot; Sec. 3.2, reproducible dot products
+ *     and their rounding);
+ *   - exspmv: the CSR sparse matrix-vector product with every row sum computed
+ *     exactly and rounded once (the SpMV kernel of Sec. 4.1 made exact like the
+ *     dot products);
+ *   - solve: Jacobi-preconditioned BiCGStab (Fig. 2) or its pipelined variant
+ *     (Fig. 3), with every axpy-like update an explicit fma (Sec. 3.3, Sec. 4.1),
+ *     stopping when ||r_j|| / ||r_0|| <= tol (Sec. 5.1).
+ * Exactness makes every result independent of the launch shape, of the order of
+ * the data and of how many workgroups cooperate: a result is a function of the
+ * inputs alone.  A plain FP64 mode (fma rows in CSR order, tree-reduced dots) is
+ * provided as the non-reproducible comparison.
+ *
+ * Conventions for every function:
+ *   - Returns an rpk_status; never aborts, exits or throws.
+ *   - Vector arguments are contiguous float64 arrays in DEVICE memory (HIP
+ *     device pointers, e.g. from torch tensors), owned by the caller.  CSR inputs
+ *     of rpk_matrix_create may be host or device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); work is
+ *     stream-ordered.  exdot/exspmv are asynchronous; solve returns when done.
+ *   - A workspace `ws` is caller-owned device memory of at least the size the
+ *     matching *_workspace_bytes function reports, zero-filled before its first
+ *     use; the library leaves it in a reusable state after each call.  One
+ *     workspace must not be used by two calls that overlap in time.
+ *   - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef RPK_H
+#define RPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPK_OK = 0,
+  RPK_ERR_ARG = 1,         /* bad argument, size, CSR structure or workspace   */
+  RPK_ERR_NOMEM = 2,       /* device allocation failed                          */
+  RPK_ERR_HIP = 3,         /* a HIP runtime call failed                         */
+  RPK_ERR_ZERO_DIAG = 4,   /* a row has no diagonal, a repeated one, or a 0     */
+  RPK_ERR_NONFINITE = 5,   /* NaN/Inf in the matrix, b, x0, or a dot product    */
+  RPK_NOT_CONVERGED = 6,   /* maxit iterations without reaching tol             */
+  RPK_BREAKDOWN = 7        /* a zero denominator (<r0,s>, rho, omega or delta)  */
+} rpk_status;
+
+typedef enum { RPK_STD = 0, RPK_PIPELINED = 1 } rpk_variant;
+typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1 } rpk_dotmode;
+
+/* Doubles recorded per iteration when rpk_opts.hist is set.
+ *   standard : sigma alpha theta phi omega rho' gamma tau beta 0 0 0
+ *   pipelined: theta phi omega rho' mu' <r0,s> <r0,z> gamma tau beta delta alpha'
+ * (Fig. 2 / Fig. 3 names; a value not computed because the loop stopped is 0.) */
+#define RPK_HIST_W 12
+
+/* Launch shape.  Results of the exact mode do not depend on it. */
+typedef struct {
+  int32_t block;  /* workgroup size, a multiple of 64 in [64, 1024]; 0 = 256 */
+  int32_t grid;   /* workgroups of the streaming kernels, >= 1; 0 = automatic */
+  int32_t fpe;    /* FPE length 1, 2, 4 or 8 (1 sends almost every term to the
+                     long accumulator); 0 = 4 */
+  int32_t graph;  /* solve: iterations per captured HIP graph launch; 0 = automatic,
+                     -1 = no graph (direct launches) */
+} rpk_launch;
+
+typedef struct {
+  double tol;          /* stop when RN(||r_j|| / ||r_0||) <= tol              */
+  int32_t maxit;       /* iteration limit (>= 0)                             */
+  int32_t variant;     /* rpk_variant                                        */
+  int32_t dots;        /* rpk_dotmode                                        */
+  int32_t timing;      /* 1: time every kernel with HIP events (no graph)    */
+  rpk_launch launch;
+  double* hist;        /* device, maxit*RPK_HIST_W doubles, or NULL          */
+  double* xr_hist;     /* device, maxit*2*n doubles: x then r after each
+                          iteration, or NULL                                 */
+} rpk_opts;
+
+#define RPK_NPHASE 8
+typedef struct {
+  int32_t status;      /* rpk_status of the solve                             */
+  int32_t iters;       /* completed iterations                                */
+  double tau0;         /* ||r_0||                                             */
+  double tau;          /* last ||r_j||                                        */
+  double true_res;     /* ||b - A x|| of the returned x (exact dots/rows)     */
+  double phase_ms[RPK_NPHASE];   /* timing mode: summed kernel times per phase */
+  int32_t phase_launches[RPK_NPHASE];
+} rpk_info;
+
+typedef struct rpk_matrix rpk_matrix;
+
+/* Library version string. */
+const char* rpk_version(void);
+
+/* Human-readable name of a status code. */
+const char* rpk_status_str(int32_t status);
+
+/* Create a matrix handle: the CSR arrays (row_ptr[n+1], col_idx[nnz], vals[nnz],
+ * zero-based, int32 indices) are copied into library-owned device memory, then
+ * checked on the device: row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing,
+ * 0 <= col < n (else RPK_ERR_ARG); finite values (else RPK_ERR_NONFINITE);
+ * exactly one diagonal entry per row, non-zero (else RPK_ERR_ZERO_DIAG).  The
+ * Jacobi preconditioner dinv_i = RN(1/a_ii) (Sec. 4, M = diag(A)) is computed on
+ * the device.  Columns within a row may come in any order and off-diagonal
+ * duplicates are summed exactly.  1 <= n < 2^31, 0 <= nnz < 2^31.
+ * ptrs_on_device: 0 = host arrays, 1 = device arrays.  Synchronous.
+ * On error *out is NULL and nothing is leaked. */
+rpk_status rpk_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* vals, int32_t ptrs_on_device, void* stream, rpk_matrix** out);
+rpk_status rpk_matrix_destroy(rpk_matrix* A);
+rpk_status rpk_matrix_dims(const rpk_matrix* A, int64_t* n, int64_t* nnz);
+/* device pointer to dinv (n doubles, owned by the handle) */
+rpk_status rpk_matrix_dinv(const rpk_matrix* A, const double** dinv);
+
+/* Workspace size of rpk_exdot for n elements and the given launch (NULL = defaults). */
+rpk_status rpk_exdot_workspace_bytes(int64_t n, const rpk_launch* launch, size_t* bytes);
+
+/* *out_dev = RN(sum_i x[i]*y[i]) of the exact sum (Sec. 2, exdot), one device double.
+ * Exact zero gives +0.0; a non-zero sum that rounds to zero keeps its sign; an
+ * overflowing sum gives +-inf; any non-finite factor gives NaN.  n < 2^32.
+ * dots = RPK_DOT_PLAIN gives the non-reproducible fma/tree-reduction value instead.
+ * Asynchronous on `stream`. */
+rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
+                     const rpk_launch* launch, void* ws, size_t ws_bytes, void* stream);
+
+/* y = A x with y_i = RN(sum_j a_ij x_j) of the exact row sum (Sec. 4.1 SpMV,
+ * exact); plain mode: sequential fma in CSR order.  x, y: n device doubles, must
+ * not overlap.  Asynchronous on `stream`. */
+rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t dots, const rpk_launch* launch,
+                      void* stream);
+
+/* Workspace size of rpk_solve for this matrix, options (variant, dots, launch). */
+rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* opts, size_t* bytes);
+
+/* Solve A x = b with PBiCGStab (Fig. 2) or p-PBiCGStab (Fig. 3), Jacobi
+ * preconditioned, from the initial guess in x; x receives the last full iterate.
+ * b, x: n device doubles.  Returns info->status (RPK_OK on convergence); on
+ * RPK_NOT_CONVERGED / RPK_BREAKDOWN / RPK_ERR_NONFINITE x holds the last full
+ * iterate.  Blocks until the solve is finished. */
+rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_opts* opts, void* ws,
+                     size_t ws_bytes, void* stream, rpk_info* info);
+
+/* Test hook: q[i] = a[i]/b[i] and s[i] = sqrt(a[i]) with the device operations the
+ * solver's scalar steps use (to check them against IEEE-754 on the host). */
+rpk_status rpk_device_divsqrt(int64_t n, const double* a, const double* b, double* q, double* s, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPK_H */

@@ -1,0 +1,58 @@
+// kern_inst.hip -- launchers of Kern<RPK_N>; compiled once per FPE length
+// (RPK_N = 0 plain FP64, 1, 2, 4, 8) so the instantiations build in parallel.
+#include "kern.h"
+
+namespace rpk {
+
+template <typename K, typename... Args>
+static rpk_status launch(K kernel, int grid, int block, size_t shm, hipStream_t s, Args... args) {
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shm, s, args...);
+  return hipGetLastError() == hipSuccess ? RPK_OK : RPK_ERR_HIP;
+}
+
+template <int N>
+rpk_status Kern<N>::dot(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* out,
+                        Red red) {
+  return launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, out, red);
+}
+
+template <int N>
+rpk_status Kern<N>::spmv(int G, int B, hipStream_t s, Csr A, const double* x, double* y) {
+  return launch(k_spmv<N>, G, B, shm_bytes(N, 0, true, B), s, A, x, y);
+}
+
+template <int N>
+rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
+  if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+  RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+  RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+  return launch(k_pipe_init3<N>, G + 1, B, shm_bytes(N, 2, true, B), s, A, V, red);
+}
+
+template <int N>
+rpk_status Kern<N>::resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
+  return launch(k_resid<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+}
+
+template <int N>
+rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
+  if (variant == RPK_STD) {
+    switch (ph) {
+      case 0: return launch(k_std_A<N>, G, B, 0, s, A, V);
+      case 1: return launch(k_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+      case 2: return launch(k_std_C<N>, G, B, 0, s, A, V);
+      case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
+      default: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+    }
+  }
+  switch (ph) {
+    case 0: return launch(k_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+    case 1: return launch(k_pipe_P2<N>, G + 1, B, shm_bytes(N, 2, true, B), s, A, V, red);
+    case 2: return launch(k_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, A, V, red);
+    default: return launch(k_pipe_P4<N>, G + 1, B, shm_bytes(N, 5, true, B), s, A, V, red);
+  }
+}
+
+template struct Kern<RPK_N>;
+
+}  // namespace rpk

@@ -1,0 +1,496 @@
+// rpk.hip -- host side of the C ABI declared in include/rpk.h.
+//
+// Solver engine: the set-up kernels run once, then the iteration kernels are
+// captured into a HIP graph holding a chunk of iterations.  Iterations run
+// entirely on the device (scalars, stop test and status live in device memory);
+// the host reads the 'done' flag once per chunk, and kernels of iterations past
+// the stop are no-ops, so the result does not depend on the chunk size.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "rpk.h"
+#include "kern.h"
+#include "setup.h"
+
+using namespace rpk;
+
+struct rpk_matrix {
+  int64_t n = 0, nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* v = nullptr;
+  double* dinv = nullptr;
+};
+
+namespace {
+
+#define HIPCHK(call)                            \
+  do {                                          \
+    if ((call) != hipSuccess) return RPK_ERR_HIP; \
+  } while (0)
+
+struct Cfg {
+  int block, grid, fpe, graph;
+};
+
+rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
+  c->block = (L && L->block) ? L->block : 256;
+  c->fpe = (L && L->fpe) ? L->fpe : 4;
+  c->graph = L ? L->graph : 0;
+  if (c->block < 64 || c->block > 1024 || (c->block % 64) != 0) return RPK_ERR_ARG;
+  if (c->fpe != 1 && c->fpe != 2 && c->fpe != 4 && c->fpe != 8) return RPK_ERR_ARG;
+  if (c->graph < -1) return RPK_ERR_ARG;
+  if (L && L->grid) {
+    if (L->grid < 1 || L->grid > 65535) return RPK_ERR_ARG;
+    c->grid = L->grid;
+  } else {
+    int64_t need = (n + c->block - 1) / c->block;
+    if (need < 1) need = 1;
+    if (need > 1024) need = 1024;
+    if (need >= 8) need &= ~7ll;
+    c->grid = (int)need;
+  }
+  return RPK_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// workspace header: state | tickets+flags | long accumulators | partials
+struct Layout {
+  size_t state, tickets, gflags, gsa, partials, vecs, total;
+};
+
+Layout layout(int grid, int64_t n, int nvec) {
+  Layout l;
+  size_t off = 0;
+  l.state = off;
+  off += up(sizeof(State));
+  l.tickets = off;
+  l.gflags = off + 8 * sizeof(unsigned);
+  off += up(8 * sizeof(unsigned) + MAX_DOTS * sizeof(int));
+  l.gsa = off;
+  off += up((size_t)MAX_DOTS * SA_D * sizeof(long long));
+  l.partials = off;
+  off += up((size_t)MAX_DOTS * 8 * grid * sizeof(double));
+  l.vecs = off;
+  off += (size_t)nvec * up((size_t)n * sizeof(double));
+  l.total = off;
+  return l;
+}
+
+Red make_red(char* ws, const Layout& l, int grid) {
+  Red r;
+  r.partials = (double*)(ws + l.partials);
+  r.gsa = (long long*)(ws + l.gsa);
+  r.gflags = (int*)(ws + l.gflags);
+  r.tickets = (unsigned*)(ws + l.tickets);
+  r.G = grid;
+  return r;
+}
+
+int nvec_of(int variant) { return variant == RPK_STD ? 8 : 16; }
+
+Csr csr_of(const rpk_matrix* A) { return Csr{A->rp, A->ci, A->v, A->dinv, (int)A->n}; }
+
+template <template <int> class F, typename... Args>
+rpk_status by_fpe(int N, Args&&... args) {
+  switch (N) {
+    case 0: return F<0>::call(args...);
+    case 1: return F<1>::call(args...);
+    case 2: return F<2>::call(args...);
+    case 4: return F<4>::call(args...);
+    case 8: return F<8>::call(args...);
+  }
+  return RPK_ERR_ARG;
+}
+
+template <int N>
+struct DotF {
+  static rpk_status call(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* o,
+                         Red r) {
+    return Kern<N>::dot(G, B, s, n, x, y, o, r);
+  }
+};
+template <int N>
+struct SpmvF {
+  static rpk_status call(int G, int B, hipStream_t s, Csr A, const double* x, double* y) {
+    return Kern<N>::spmv(G, B, s, A, x, y);
+  }
+};
+template <int N>
+struct InitF {
+  static rpk_status call(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red r) {
+    return Kern<N>::init(variant, G, B, s, A, V, r);
+  }
+};
+template <int N>
+struct PhaseF {
+  static rpk_status call(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red r) {
+    return Kern<N>::phase(variant, ph, G, B, s, A, V, r);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// graph cache: one executable graph per (matrix, buffers, shape, chunk)
+// ---------------------------------------------------------------------------
+using GraphKey = std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, int, int, int,
+                            int, int>;
+std::mutex g_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+hipStream_t g_capture = nullptr;
+State* g_pinned = nullptr;
+
+rpk_status ensure_globals() {
+  if (!g_capture) HIPCHK(hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking));
+  if (!g_pinned) HIPCHK(hipHostMalloc((void**)&g_pinned, sizeof(State), hipHostMallocDefault));
+  return RPK_OK;
+}
+
+void drop_graphs(const rpk_matrix* A) {
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (std::get<0>(it->first) == (const void*)A) {
+      hipGraphExecDestroy(it->second);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* rpk_version(void) { return "rpk 0.1 (gfx950, exact FPE + long accumulator)"; }
+
+const char* rpk_status_str(int32_t s) {
+  switch (s) {
+    case RPK_OK: return "RPK_OK";
+    case RPK_ERR_ARG: return "RPK_ERR_ARG";
+    case RPK_ERR_NOMEM: return "RPK_ERR_NOMEM";
+    case RPK_ERR_HIP: return "RPK_ERR_HIP";
+    case RPK_ERR_ZERO_DIAG: return "RPK_ERR_ZERO_DIAG";
+    case RPK_ERR_NONFINITE: return "RPK_ERR_NONFINITE";
+    case RPK_NOT_CONVERGED: return "RPK_NOT_CONVERGED";
+    case RPK_BREAKDOWN: return "RPK_BREAKDOWN";
+  }
+  return "RPK_UNKNOWN";
+}
+
+static void free_matrix(rpk_matrix* A) {
+  if (!A) return;
+  if (A->rp) (void)hipFree(A->rp);
+  if (A->ci) (void)hipFree(A->ci);
+  if (A->v) (void)hipFree(A->v);
+  if (A->dinv) (void)hipFree(A->dinv);
+  delete A;
+}
+
+static rpk_status create_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
+                              int32_t on_dev, hipStream_t s, rpk_matrix* A) {
+  A->n = n;
+  A->nnz = nnz;
+  if (hipMalloc((void**)&A->rp, (size_t)(n + 1) * 4) != hipSuccess) return RPK_ERR_NOMEM;
+  if (hipMalloc((void**)&A->ci, (size_t)(nnz > 0 ? nnz : 1) * 4) != hipSuccess) return RPK_ERR_NOMEM;
+  if (hipMalloc((void**)&A->v, (size_t)(nnz > 0 ? nnz : 1) * 8) != hipSuccess) return RPK_ERR_NOMEM;
+  if (hipMalloc((void**)&A->dinv, (size_t)n * 8) != hipSuccess) return RPK_ERR_NOMEM;
+  const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(hipMemcpyAsync(A->rp, rp, (size_t)(n + 1) * 4, kind, s));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpyAsync(A->ci, ci, (size_t)nnz * 4, kind, s));
+    HIPCHK(hipMemcpyAsync(A->v, v, (size_t)nnz * 8, kind, s));
+  }
+  int* flags = nullptr;
+  if (hipMalloc((void**)&flags, 2 * sizeof(int)) != hipSuccess) return RPK_ERR_NOMEM;
+  int hflags[2] = {0, 0};
+  rpk_status st = RPK_OK;
+  do {
+    if (hipMemsetAsync(flags, 0, 2 * sizeof(int), s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    const int B = 256;
+    const int G1 = (int)((n + 1 + B - 1) / B);
+    hipLaunchKernelGGL(k_check_rowptr, dim3(G1), dim3(B), 0, s, A->rp, (int)n, (int)nnz, flags);
+    if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hipMemcpyAsync(hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hflags[0]) { st = RPK_ERR_ARG; break; }  // row_ptr unusable: do not read the rows
+    const int G2 = (int)((n + B - 1) / B);
+    hipLaunchKernelGGL(k_setup_rows, dim3(G2), dim3(B), 0, s, A->rp, A->ci, A->v, (int)n, A->dinv, flags + 1);
+    if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hipMemcpyAsync(hflags + 1, flags + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hflags[1] & CHK_ARG) st = RPK_ERR_ARG;
+    else if (hflags[1] & CHK_NONFINITE) st = RPK_ERR_NONFINITE;
+    else if (hflags[1] & CHK_DIAG) st = RPK_ERR_ZERO_DIAG;
+  } while (0);
+  (void)hipFree(flags);
+  return st;
+}
+
+rpk_status rpk_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* vals, int32_t ptrs_on_device, void* stream, rpk_matrix** out) {
+  if (!out) return RPK_ERR_ARG;
+  *out = nullptr;
+  if (n < 1 || n >= (1ll << 31) || nnz < 0 || nnz >= (1ll << 31) || !row_ptr) return RPK_ERR_ARG;
+  if (nnz > 0 && (!col_idx || !vals)) return RPK_ERR_ARG;
+  rpk_matrix* A = new (std::nothrow) rpk_matrix();
+  if (!A) return RPK_ERR_NOMEM;
+  rpk_status st = create_impl(n, nnz, row_ptr, col_idx, vals, ptrs_on_device, (hipStream_t)stream, A);
+  if (st != RPK_OK) {
+    free_matrix(A);
+    return st;
+  }
+  *out = A;
+  return RPK_OK;
+}
+
+rpk_status rpk_matrix_destroy(rpk_matrix* A) {
+  if (!A) return RPK_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    drop_graphs(A);
+  }
+  free_matrix(A);
+  return RPK_OK;
+}
+
+rpk_status rpk_matrix_dims(const rpk_matrix* A, int64_t* n, int64_t* nnz) {
+  if (!A) return RPK_ERR_ARG;
+  if (n) *n = A->n;
+  if (nnz) *nnz = A->nnz;
+  return RPK_OK;
+}
+
+rpk_status rpk_matrix_dinv(const rpk_matrix* A, const double** dinv) {
+  if (!A || !dinv) return RPK_ERR_ARG;
+  *dinv = A->dinv;
+  return RPK_OK;
+}
+
+rpk_status rpk_exdot_workspace_bytes(int64_t n, const rpk_launch* launch, size_t* bytes) {
+  if (!bytes || n < 0) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(launch, n, &c));
+  *bytes = layout(c.grid, 0, 0).total;
+  return RPK_OK;
+}
+
+rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
+                     const rpk_launch* launch_cfg, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= (1ll << 32) || !out_dev || !ws || (n > 0 && (!x || !y))) return RPK_ERR_ARG;
+  if (dots != RPK_DOT_EXACT && dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(launch_cfg, n, &c));
+  const Layout l = layout(c.grid, 0, 0);
+  if (ws_bytes < l.total) return RPK_ERR_ARG;
+  Red red = make_red((char*)ws, l, c.grid);
+  const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  return by_fpe<DotF>(N, c.grid, c.block, (hipStream_t)stream, (long long)n, x, y, out_dev, red);
+}
+
+rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t dots, const rpk_launch* launch_cfg,
+                      void* stream) {
+  if (!A || !x || !y || x == y) return RPK_ERR_ARG;
+  if (dots != RPK_DOT_EXACT && dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(launch_cfg, A->n, &c));
+  const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, csr_of(A), x, y);
+}
+
+rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* o, size_t* bytes) {
+  if (!A || !o || !bytes) return RPK_ERR_ARG;
+  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(&o->launch, A->n, &c));
+  *bytes = layout(c.grid, A->n, nvec_of(o->variant)).total;
+  return RPK_OK;
+}
+
+static Vecs carve_vecs(char* ws, const Layout& l, int64_t n, int variant, double* x, const double* b,
+                       const rpk_opts* o) {
+  Vecs V;
+  std::memset(&V, 0, sizeof(V));
+  const size_t step = up((size_t)n * sizeof(double));
+  double* p[16];
+  for (int k = 0; k < nvec_of(variant); ++k) p[k] = (double*)(ws + l.vecs + k * step);
+  V.r0 = p[0]; V.r = p[1]; V.p = p[2]; V.ph = p[3]; V.s = p[4]; V.q = p[5]; V.qh = p[6]; V.y = p[7];
+  if (variant == RPK_PIPELINED) {
+    V.rh = p[8]; V.w = p[9]; V.wh = p[10]; V.t = p[11]; V.sh = p[12]; V.z = p[13]; V.zh = p[14]; V.v = p[15];
+  }
+  V.x = x;
+  V.b = b;
+  V.st = (State*)(ws + l.state);
+  V.hist = o->hist;
+  V.xr = o->xr_hist;
+  return V;
+}
+
+rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_opts* o, void* ws, size_t ws_bytes,
+                     void* stream, rpk_info* info) {
+  if (!A || !b || !x || !o || !ws || !info) return RPK_ERR_ARG;
+  std::memset(info, 0, sizeof(*info));
+  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  if (o->maxit < 0 || !(o->tol >= 0.0)) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(&o->launch, A->n, &c));
+  const Layout l = layout(c.grid, A->n, nvec_of(o->variant));
+  if (ws_bytes < l.total) return RPK_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  RET_IF(ensure_globals());
+
+  char* w = (char*)ws;
+  const int variant = o->variant;
+  const int N = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  const int G = c.grid, B = c.block;
+  const int nph = (variant == RPK_STD) ? 5 : 4;
+  Red red = make_red(w, l, G);
+  Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
+  Csr Ac = csr_of(A);
+
+  // reduction scratch to zero; caller-visible histories to zero
+  hipLaunchKernelGGL(k_zero_words, dim3(16), dim3(256), 0, s, (unsigned*)(w + l.tickets),
+                     (long long)((l.partials - l.tickets) / sizeof(unsigned)));
+  HIPCHK(hipGetLastError());
+  if (o->hist) {
+    hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, s, o->hist, (long long)o->maxit * HIST_W, 0.0);
+    HIPCHK(hipGetLastError());
+  }
+  if (o->xr_hist) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, o->xr_hist, (long long)o->maxit * 2 * A->n, 0.0);
+    HIPCHK(hipGetLastError());
+  }
+  if (variant == RPK_PIPELINED) {  // vectors of iteration -1 start at zero
+    const size_t step = up((size_t)A->n * sizeof(double));
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, (double*)(w + l.vecs),
+                       (long long)(16 * step / sizeof(double)), 0.0);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_state_setup, dim3(1), dim3(64), 0, s, V.st, o->tol, o->maxit, variant);
+  HIPCHK(hipGetLastError());
+
+  hipEvent_t ev[RPK_NPHASE + 1] = {};
+  const bool timing = o->timing != 0;
+  if (timing)
+    for (int k = 0; k <= RPK_NPHASE; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  auto cleanup = [&]() {
+    if (timing)
+      for (int k = 0; k <= RPK_NPHASE; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+  };
+
+  rpk_status st = RPK_OK;
+  do {
+    if (timing && hipEventRecord(ev[0], s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    st = by_fpe<InitF>(N, variant, G, B, s, Ac, V, red);
+    if (st != RPK_OK) break;
+    if (timing) {
+      if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[0], ev[1]);
+      info->phase_ms[6] += ms;
+      info->phase_launches[6] += 1;
+    }
+    if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    const bool use_graph = !timing && c.graph >= 0;
+    int chunk = c.graph > 0 ? c.graph : 4;
+    long long launched = 0;
+    while (!g_pinned->done) {
+      if (launched > (long long)o->maxit + 8) { st = RPK_ERR_HIP; break; }  // cannot happen: device stops at maxit
+      if (timing) {
+        for (int ph = 0; ph < nph && st == RPK_OK; ++ph) {
+          if (hipEventRecord(ev[ph], s) != hipSuccess) st = RPK_ERR_HIP;
+          if (st == RPK_OK) st = by_fpe<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
+        }
+        if (st != RPK_OK) break;
+        if (hipEventRecord(ev[nph], s) != hipSuccess || hipEventSynchronize(ev[nph]) != hipSuccess) {
+          st = RPK_ERR_HIP;
+          break;
+        }
+        for (int ph = 0; ph < nph; ++ph) {
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
+          info->phase_ms[ph] += ms;
+          info->phase_launches[ph] += 1;
+        }
+        launched += 1;
+      } else if (use_graph) {
+        GraphKey key{A, b, x, ws, o->hist, o->xr_hist, variant, N, G, B, chunk};
+        auto it = g_graphs.find(key);
+        hipGraphExec_t exec = nullptr;
+        if (it == g_graphs.end()) {
+          hipGraph_t graph = nullptr;
+          if (hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal) != hipSuccess) { st = RPK_ERR_HIP; break; }
+          rpk_status cst = RPK_OK;
+          for (int k = 0; k < chunk && cst == RPK_OK; ++k)
+            for (int ph = 0; ph < nph && cst == RPK_OK; ++ph)
+              cst = by_fpe<PhaseF>(N, variant, ph, G, B, g_capture, Ac, V, red);
+          const hipError_t ec = hipStreamEndCapture(g_capture, &graph);
+          if (cst != RPK_OK || ec != hipSuccess) { st = RPK_ERR_HIP; if (graph) hipGraphDestroy(graph); break; }
+          const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          hipGraphDestroy(graph);
+          if (ei != hipSuccess) { st = RPK_ERR_HIP; break; }
+          g_graphs[key] = exec;
+        } else {
+          exec = it->second;
+        }
+        if (hipGraphLaunch(exec, s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+        launched += chunk;
+      } else {
+        const int k_iter = chunk;
+        for (int k = 0; k < k_iter && st == RPK_OK; ++k)
+          for (int ph = 0; ph < nph && st == RPK_OK; ++ph)
+            st = by_fpe<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
+        if (st != RPK_OK) break;
+        launched += k_iter;
+      }
+      if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+      if (c.graph == 0 && chunk < 32) chunk *= 2;
+    }
+    if (st != RPK_OK) break;
+    // true residual of the returned iterate, exact
+    if (timing && hipEventRecord(ev[0], s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    st = Kern<4>::resid(G, B, s, Ac, V, red);
+    if (st != RPK_OK) break;
+    if (timing) {
+      if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[0], ev[1]);
+      info->phase_ms[7] += ms;
+      info->phase_launches[7] += 1;
+    }
+    if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+  } while (0);
+  cleanup();
+  if (st != RPK_OK) return st;
+  const State& h = *g_pinned;
+  info->status = h.status;
+  info->iters = h.iter;
+  info->tau0 = h.tau0;
+  info->tau = h.tau;
+  info->true_res = h.true_res;
+  return (rpk_status)h.status;
+}
+
+rpk_status rpk_device_divsqrt(int64_t n, const double* a, const double* b, double* q, double* r, void* stream) {
+  if (n < 0 || (n > 0 && (!a || !b || !q || !r))) return RPK_ERR_ARG;
+  if (n == 0) return RPK_OK;
+  hipLaunchKernelGGL(k_divsqrt, dim3(1024), dim3(256), 0, (hipStream_t)stream, (long long)n, a, b, q, r);
+  return hipGetLastError() == hipSuccess ? RPK_OK : RPK_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,497 @@
+// solver.h -- fused phase kernels of PBiCGStab (Fig. 2) and p-PBiCGStab (Fig. 3).
+//
+// Standard loop, five kernels per iteration:
+//   A: S12 (from the second iteration on) + S1        p, p^ update
+//   B: S2 SpMV + S3 dot <r0,s>; last block: alpha
+//   C: S4 + S5                                         q, q^
+//   D: S6 SpMV + S7 dots <q,y>, <y,y>; last block: omega
+//   E: S8 + S9 + S10/S11 dots <r0,r>, <r,r>; last block: tau, stop test, beta
+// Pipelined loop, four kernels per iteration; each reduction is finished by one
+// extra workgroup of the following SpMV kernel, so it overlaps that SpMV (the
+// single-GPU counterpart of the Iallreduce/Wait pairs of Sec. 4.2):
+//   P1: S1..S7 + S9 + S8 dot partials
+//   P2: S10 SpMV  || S11 omega
+//   P3: S12..S15 + S17 + S16 dot partials (and <r,r> for tau)
+//   P4: S18 SpMV  || S19 tau, stop test, beta, delta, alpha
+// Every update is the explicit fma written next to it; scalar steps are single
+// IEEE operations in one thread, in the order of the figures.
+#pragma once
+#include "kernels.h"
+
+namespace rpk {
+
+__device__ __forceinline__ double qnan() { return __longlong_as_double(0x7ff8000000000000ll); }
+
+struct Vecs {
+  // standard: r0 r p ph s q qh y ; pipelined adds rh w wh t sh z zh v
+  double *r0, *r, *p, *ph, *s, *q, *qh, *y;
+  double *rh, *w, *wh, *t, *sh, *z, *zh, *v;
+  double* x;
+  const double* b;
+  State* st;
+  double* hist;  // [maxit][HIST_W] or null
+  double* xr;    // [maxit][2][n] or null
+};
+
+__device__ __forceinline__ double* hist_row(const Vecs& V, int iter) {
+  return V.hist ? V.hist + (size_t)iter * HIST_W : nullptr;
+}
+
+__device__ __forceinline__ void record_xr(const Vecs& V, int iter, int n, int row, double xv, double rv) {
+  if (V.xr) {
+    V.xr[((size_t)iter * 2 + 0) * n + row] = xv;
+    V.xr[((size_t)iter * 2 + 1) * n + row] = rv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// scalar steps (thread 0 of the finishing workgroup)
+// ---------------------------------------------------------------------------
+__device__ inline void stop(State* st, int status) {
+  st->status = status;
+  st->done = 1;
+}
+
+// r0 := b - A x0, tau0 := ||r0|| ; loop entry test
+__device__ inline void step_entry(State* st, double rho) {
+  if (isnan(rho)) {
+    st->tau0 = st->tau = qnan();
+    stop(st, ST_NONFINITE);
+    return;
+  }
+  st->rho = rho;
+  st->tau0 = sqrt(rho);
+  st->tau = st->tau0;
+  if (st->tau0 == 0.0) stop(st, ST_OK);
+}
+
+__device__ inline void step_loop_entry(State* st) {
+  if (st->done) return;
+  if (st->tau / st->tau0 <= st->tol) stop(st, ST_OK);
+  else if (st->maxit <= 0) stop(st, ST_NOT_CONVERGED);
+}
+
+// S3: alpha = rho / <r0, s>
+__device__ inline void step_std_alpha(State* st, double* h, double sigma) {
+  if (h) h[0] = sigma;
+  if (isnan(sigma)) return stop(st, ST_NONFINITE);
+  if (sigma == 0.0) return stop(st, ST_BREAKDOWN);
+  st->alpha = st->rho / sigma;
+  if (h) h[1] = st->alpha;
+}
+
+// S7 / S11: omega = <q,y> / <y,y>  (0 when <y,y> = 0)
+__device__ inline void step_omega(State* st, double* h, double theta, double phi, int at) {
+  if (h) {
+    h[at] = theta;
+    h[at + 1] = phi;
+  }
+  if (isnan(theta) || isnan(phi)) return stop(st, ST_NONFINITE);
+  st->omega = (phi == 0.0) ? 0.0 : theta / phi;
+  if (h) h[at + 2] = st->omega;
+}
+
+// S10 + S11 and the stop test; beta for S12
+__device__ inline void step_std_beta(State* st, double* h, double rho_new, double gamma) {
+  if (h) {
+    h[5] = rho_new;
+    h[6] = gamma;
+  }
+  st->iter += 1;
+  if (isnan(rho_new) || isnan(gamma)) return stop(st, ST_NONFINITE);
+  st->tau = sqrt(gamma);
+  if (h) h[7] = st->tau;
+  if (st->tau / st->tau0 <= st->tol) return stop(st, ST_OK);
+  if (st->iter >= st->maxit) return stop(st, ST_NOT_CONVERGED);
+  if (st->rho == 0.0 || st->omega == 0.0) return stop(st, ST_BREAKDOWN);
+  st->beta = (rho_new / st->rho) * (st->alpha / st->omega);
+  if (h) h[8] = st->beta;
+  st->rho = rho_new;
+}
+
+// pipelined set-up: alpha0 = rho / <r0, w>
+__device__ inline void step_pipe_entry(State* st, double rho, double mu) {
+  step_entry(st, rho);
+  if (st->done) return;
+  if (isnan(mu)) return stop(st, ST_NONFINITE);
+  if (mu == 0.0) return stop(st, ST_BREAKDOWN);
+  st->alpha = rho / mu;
+  st->beta = 0.0;
+  st->omega = 0.0;
+  step_loop_entry(st);
+}
+
+// S19
+__device__ inline void step_pipe_s19(State* st, double* h, const double* d) {
+  const double rho_new = d[0], mu_new = d[1], vs = d[2], zeta = d[3], gamma = d[4];
+  if (h)
+    for (int k = 0; k < 5; ++k) h[3 + k] = d[k];
+  st->iter += 1;
+  for (int k = 0; k < 5; ++k)
+    if (isnan(d[k])) return stop(st, ST_NONFINITE);
+  st->tau = sqrt(gamma);
+  if (h) h[8] = st->tau;
+  if (st->tau / st->tau0 <= st->tol) return stop(st, ST_OK);
+  if (st->iter >= st->maxit) return stop(st, ST_NOT_CONVERGED);
+  if (st->rho == 0.0 || st->omega == 0.0) return stop(st, ST_BREAKDOWN);
+  const double beta = (rho_new / st->rho) * (st->alpha / st->omega);
+  const double delta = fma(beta, fma(-st->omega, zeta, vs), mu_new);
+  if (h) {
+    h[9] = beta;
+    h[10] = delta;
+  }
+  if (delta == 0.0) return stop(st, ST_BREAKDOWN);
+  st->beta = beta;
+  st->alpha = rho_new / delta;
+  if (h) h[11] = st->alpha;
+  st->rho = rho_new;
+}
+
+// ---------------------------------------------------------------------------
+// standard loop
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double t = rows_wave<N>(A, V.x, i, ok, s.wsa);
+    if (ok) {
+      const double ri = V.b[i] - t;
+      V.r[i] = ri;
+      V.r0[i] = ri;
+      V.p[i] = ri;
+      d[0].add(ri, ri, s.sa, &s.flag[0]);
+    }
+  }
+  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[1])) return;
+  block_finalize<N, 1>(s, red, 0);
+  if (threadIdx.x == 0) {
+    step_entry(V.st, s.res[0]);
+    step_loop_entry(V.st);
+  }
+}
+
+// A: S12 (iterations after the first) and S1
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
+  const State* st = V.st;
+  if (st->done) return;
+  const bool upd = st->iter > 0;
+  const double beta = st->beta, omega = st->omega;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    double p = V.p[i];
+    if (upd) {
+      p = fma(beta, fma(-omega, V.s[i], p), V.r[i]);
+      V.p[i] = p;
+    }
+    V.ph[i] = A.dinv[i] * p;
+  }
+}
+
+// B: S2 + S3
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double si = rows_wave<N>(A, V.ph, i, ok, s.wsa);
+    if (ok) {
+      V.s[i] = si;
+      d[0].add(V.r0[i], si, s.sa, &s.flag[0]);
+    }
+  }
+  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[2])) return;
+  block_finalize<N, 1>(s, red, 0);
+  if (threadIdx.x == 0) step_std_alpha(V.st, hist_row(V, V.st->iter), s.res[0]);
+}
+
+// C: S4 + S5
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
+  const State* st = V.st;
+  if (st->done) return;
+  const double alpha = st->alpha;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    const double q = fma(-alpha, V.s[i], V.r[i]);
+    V.q[i] = q;
+    V.qh[i] = A.dinv[i] * q;
+  }
+}
+
+// D: S6 + S7
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  shm_init(s, 2);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double yi = rows_wave<N>(A, V.qh, i, ok, s.wsa);
+    if (ok) {
+      V.y[i] = yi;
+      d[0].add(V.q[i], yi, s.sa, &s.flag[0]);
+      d[1].add(yi, yi, s.sa + SA_D, &s.flag[1]);
+    }
+  }
+  if (!block_publish<N, 2>(d, s, red, 0, &red.tickets[3])) return;
+  block_finalize<N, 2>(s, red, 0);
+  if (threadIdx.x == 0) step_omega(V.st, hist_row(V, V.st->iter), s.res[0], s.res[1], 2);
+}
+
+// E: S8 + S9 + S10/S11
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
+  const State* st = V.st;
+  if (st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  shm_init(s, 2);
+  const double alpha = st->alpha, omega = st->omega;
+  const int iter = st->iter;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    const double x = fma(omega, V.qh[i], fma(alpha, V.ph[i], V.x[i]));
+    const double r = fma(-omega, V.y[i], V.q[i]);
+    V.x[i] = x;
+    V.r[i] = r;
+    record_xr(V, iter, A.n, i, x, r);
+    d[0].add(V.r0[i], r, s.sa, &s.flag[0]);
+    d[1].add(r, r, s.sa + SA_D, &s.flag[1]);
+  }
+  if (!block_publish<N, 2>(d, s, red, 0, &red.tickets[4])) return;
+  block_finalize<N, 2>(s, red, 0);
+  if (threadIdx.x == 0) step_std_beta(V.st, hist_row(V, iter), s.res[0], s.res[1]);
+}
+
+// true residual ||b - A x|| (reported at exit)
+template <int N>
+__global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double t = rows_wave<N>(A, V.x, i, ok, s.wsa);
+    if (ok) {
+      const double e = V.b[i] - t;
+      d[0].add(e, e, s.sa, &s.flag[0]);
+    }
+  }
+  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[5])) return;
+  block_finalize<N, 1>(s, red, 0);
+  if (threadIdx.x == 0) V.st->true_res = sqrt(s.res[0]);
+}
+
+// ---------------------------------------------------------------------------
+// pipelined loop
+// ---------------------------------------------------------------------------
+// set-up 1: r = b - A x0, r0 = r, r^ = M^-1 r ; partial <r0, r> (slot 0)
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double t = rows_wave<N>(A, V.x, i, ok, s.wsa);
+    if (ok) {
+      const double ri = V.b[i] - t;
+      V.r[i] = ri;
+      V.r0[i] = ri;
+      V.rh[i] = A.dinv[i] * ri;
+      d[0].add(ri, ri, s.sa, &s.flag[0]);
+    }
+  }
+  block_publish<N, 1>(d, s, red, 0, nullptr);
+}
+
+// set-up 2: w = A r^, w^ = M^-1 w ; partial <r0, w> (slot 1)
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double wi = rows_wave<N>(A, V.rh, i, ok, s.wsa);
+    if (ok) {
+      V.w[i] = wi;
+      V.wh[i] = A.dinv[i] * wi;
+      d[0].add(V.r0[i], wi, s.sa, &s.flag[0]);
+    }
+  }
+  block_publish<N, 1>(d, s, red, 1, nullptr);
+}
+
+// SpMV kernels of the pipelined loop: workgroup with logical index 0 finishes
+// the pending reduction, the others compute out = A in.
+template <int N, int K>
+__device__ __forceinline__ int spmv_or_finish(const Csr& A, const double* in, double* out, const Shm<N>& s,
+                                              const Red& red) {
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  if (L == 0) {
+    block_finalize<N, K>(s, red, 0);
+    return 1;
+  }
+  const Range R = block_rows(A.n, L - 1, gridDim.x - 1);
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double v = rows_wave<N>(A, in, i, ok, s.wsa);
+    if (ok) out[i] = v;
+  }
+  return 0;
+}
+
+// set-up 3: t = A w^ || alpha0 = <r0,r0> / <r0,w>
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init3(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  shm_init(s, 2);
+  if (spmv_or_finish<N, 2>(A, V.wh, V.t, s, red) && threadIdx.x == 0)
+    step_pipe_entry(V.st, s.res[0], s.res[1]);
+}
+
+// P1: S1..S7, S9 and the partials of S8 (slots 0, 1)
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
+  const State* st = V.st;
+  if (st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  shm_init(s, 2);
+  const double alpha = st->alpha, beta = st->beta, omega = st->omega;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i];
+    const double ph = fma(beta, fma(-omega, V.sh[i], V.ph[i]), rh);  // S1
+    const double sv = fma(beta, fma(-omega, V.z[i], V.s[i]), w);      // S2
+    const double sh = fma(beta, fma(-omega, V.zh[i], V.sh[i]), wh);  // S3
+    const double z = fma(beta, fma(-omega, V.v[i], V.z[i]), V.t[i]);  // S4
+    const double q = fma(-alpha, sv, V.r[i]);                         // S5
+    const double qh = fma(-alpha, sh, rh);                            // S6
+    const double y = fma(-alpha, z, w);                               // S7
+    V.ph[i] = ph;
+    V.s[i] = sv;
+    V.sh[i] = sh;
+    V.z[i] = z;
+    V.q[i] = q;
+    V.qh[i] = qh;
+    V.y[i] = y;
+    V.zh[i] = A.dinv[i] * z;                                          // S9
+    d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
+    d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
+  }
+  block_publish<N, 2>(d, s, red, 0, nullptr);
+}
+
+// P2: S10 v = A z^ || S11 omega
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P2(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  shm_init(s, 2);
+  if (spmv_or_finish<N, 2>(A, V.zh, V.v, s, red) && threadIdx.x == 0)
+    step_omega(V.st, hist_row(V, V.st->iter), s.res[0], s.res[1], 0);
+}
+
+// P3: S12..S15, S17 and the partials of S16 + <r,r> (slots 0..4)
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
+  const State* st = V.st;
+  if (st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 5, false);
+  shm_init(s, 5);
+  const double alpha = st->alpha, omega = st->omega;
+  const int iter = st->iter;
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  const Range R = block_rows(A.n, L, gridDim.x);
+  Dot<N> d[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) d[j].zero();
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    const double qh = V.qh[i], y = V.y[i], r0 = V.r0[i];
+    const double x = fma(omega, qh, fma(alpha, V.ph[i], V.x[i]));      // S12
+    const double r = fma(-omega, y, V.q[i]);                           // S13
+    const double rh = fma(-omega, fma(-alpha, V.zh[i], V.wh[i]), qh);  // S14
+    const double w = fma(-omega, fma(-alpha, V.v[i], V.t[i]), y);      // S15
+    V.x[i] = x;
+    V.r[i] = r;
+    V.rh[i] = rh;
+    V.w[i] = w;
+    V.wh[i] = A.dinv[i] * w;                                           // S17
+    record_xr(V, iter, A.n, i, x, r);
+    d[0].add(r0, r, s.sa, &s.flag[0]);                                 // S16
+    d[1].add(r0, w, s.sa + SA_D, &s.flag[1]);
+    d[2].add(r0, V.s[i], s.sa + 2 * SA_D, &s.flag[2]);
+    d[3].add(r0, V.z[i], s.sa + 3 * SA_D, &s.flag[3]);
+    d[4].add(r, r, s.sa + 4 * SA_D, &s.flag[4]);
+  }
+  block_publish<N, 5>(d, s, red, 0, nullptr);
+}
+
+// P4: S18 t = A w^ || S19
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P4(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 5, true);
+  shm_init(s, 5);
+  if (spmv_or_finish<N, 5>(A, V.wh, V.t, s, red) && threadIdx.x == 0)
+    step_pipe_s19(V.st, hist_row(V, V.st->iter), s.res);
+}
+
+}  // namespace rpk

@@ -1,0 +1,231 @@
+"""Python binding of librpk.so (argument marshalling only).
+
+Every operation runs in the library's HIP kernels; torch is used for device
+memory and streams.  If the shared library is missing the import of this module
+fails: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpk.so")
+
+STD, PIPELINED = 0, 1
+EXACT, PLAIN = 0, 1
+HIST_W = 12
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_ZERO_DIAG",
+          5: "ERR_NONFINITE", 6: "NOT_CONVERGED", 7: "BREAKDOWN"}
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("fpe", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("dots", ctypes.c_int32), ("timing", ctypes.c_int32), ("launch", Launch),
+                ("hist", ctypes.c_void_p), ("xr_hist", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau0", ctypes.c_double),
+                ("tau", ctypes.c_double), ("true_res", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 8), ("phase_launches", ctypes.c_int32 * 8)]
+
+
+EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
+           "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot",
+           "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_device_divsqrt"]
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load librpk.so (torch is imported first so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("librpk.so is not built (%s): run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    S = ctypes.c_size_t
+    lib.rpk_version.restype = ctypes.c_char_p
+    lib.rpk_status_str.restype = ctypes.c_char_p
+    lib.rpk_status_str.argtypes = [I32]
+    lib.rpk_matrix_create.argtypes = [I64, I64, P, P, P, I32, P, ctypes.POINTER(P)]
+    lib.rpk_matrix_destroy.argtypes = [P]
+    lib.rpk_matrix_dims.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.rpk_matrix_dinv.argtypes = [P, ctypes.POINTER(P)]
+    lib.rpk_exdot_workspace_bytes.argtypes = [I64, ctypes.POINTER(Launch), ctypes.POINTER(S)]
+    lib.rpk_exdot.argtypes = [I64, P, P, P, I32, ctypes.POINTER(Launch), P, S, P]
+    lib.rpk_exspmv.argtypes = [P, P, P, I32, ctypes.POINTER(Launch), P]
+    lib.rpk_solve_workspace_bytes.argtypes = [P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
+    lib.rpk_solve.argtypes = [P, P, P, ctypes.POINTER(Opts), P, S, P, ctypes.POINTER(Info)]
+    lib.rpk_device_divsqrt.argtypes = [I64, P, P, P, P, P]
+    for name in EXPORTS[2:]:
+        getattr(lib, name).restype = I32
+    _lib = lib
+    return lib
+
+
+class RpkError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s: %s" % (where, STATUS.get(code, code)))
+
+
+def _check(code, where):
+    if code != 0:
+        raise RpkError(code, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _launch(block=0, grid=0, fpe=0, graph=0):
+    return Launch(int(block), int(grid), int(fpe), int(graph))
+
+
+def _dev(t):
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return t
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes, key):
+    """Zero-filled device workspace, reused (the library leaves it reusable)."""
+    t = _ws_cache.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        _ws_cache[key] = t
+    return t
+
+
+class Matrix:
+    """CSR matrix handle owned by the library (device copy + Jacobi dinv)."""
+
+    def __init__(self, row_ptr, col_idx, vals):
+        lib = load()
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        self.n = rp.size - 1
+        self.nnz = ci.size
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        code = lib.rpk_matrix_create(self.n, self.nnz, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0,
+                                     _stream(), ctypes.byref(h))
+        self.handle = h
+        _check(code, "rpk_matrix_create")
+
+    def dinv(self):
+        """Copy of the Jacobi vector dinv_i = RN(1/a_ii) computed by the library."""
+        p = ctypes.c_void_p()
+        _check(load().rpk_matrix_dinv(self.handle, ctypes.byref(p)), "rpk_matrix_dinv")
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        _copy_device(p.value, out)
+        return out
+
+    def close(self):
+        if self.handle:
+            load().rpk_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _copy_device(src_ptr, dst):
+    """Copy dst.numel() doubles from a raw device pointer into tensor dst (hipMemcpy)."""
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    code = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), dst.numel() * 8, 3)
+    if code != 0:
+        raise RuntimeError("hipMemcpy failed: %d" % code)
+
+
+def exdot(x, y, dots=EXACT, block=0, grid=0, fpe=0):
+    """Correctly rounded <x, y> (exact mode) as a 0-dim device tensor."""
+    lib = load()
+    x, y = _dev(x), _dev(y)
+    assert x.numel() == y.numel()
+    L = _launch(block, grid, fpe)
+    nb = ctypes.c_size_t()
+    _check(lib.rpk_exdot_workspace_bytes(x.numel(), ctypes.byref(L), ctypes.byref(nb)), "workspace")
+    ws = _workspace(nb.value, ("dot", x.device.index))
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(lib.rpk_exdot(x.numel(), _ptr(x), _ptr(y), _ptr(out), int(dots), ctypes.byref(L), _ptr(ws),
+                         ws.numel(), _stream()), "rpk_exdot")
+    return out
+
+
+def exspmv(A, x, out=None, dots=EXACT, block=0, grid=0, fpe=0):
+    """y = A x with exactly rounded rows (exact mode)."""
+    lib = load()
+    x = _dev(x)
+    y = torch.empty(A.n, dtype=torch.float64, device=x.device) if out is None else out
+    L = _launch(block, grid, fpe)
+    _check(lib.rpk_exspmv(A.handle, _ptr(x), _ptr(y), int(dots), ctypes.byref(L), _stream()), "rpk_exspmv")
+    return y
+
+
+def solve(A, b, x0=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, grid=0, fpe=0,
+          graph=0, record=False, record_xr=False, timing=False):
+    """Solve A x = b.  Returns (x, info) with info a dict; info['hist'] / ['xr'] are
+    device tensors when recording was requested."""
+    lib = load()
+    b = _dev(b)
+    x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else _dev(x0).clone()
+    m = max(int(maxit), 1)
+    hist = torch.zeros((m, HIST_W), dtype=torch.float64, device=b.device) if record else None
+    xr = torch.zeros((m, 2, A.n), dtype=torch.float64, device=b.device) if record_xr else None
+    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0,
+             _launch(block, grid, fpe, graph),
+             ctypes.c_void_p(hist.data_ptr()) if hist is not None else None,
+             ctypes.c_void_p(xr.data_ptr()) if xr is not None else None)
+    nb = ctypes.c_size_t()
+    _check(lib.rpk_solve_workspace_bytes(A.handle, ctypes.byref(o), ctypes.byref(nb)), "workspace")
+    ws = _workspace(nb.value, ("solve", b.device.index))
+    info = Info()
+    code = lib.rpk_solve(A.handle, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel(), _stream(),
+                         ctypes.byref(info))
+    if code in (1, 2, 3):
+        _check(code, "rpk_solve")
+    res = {"status": STATUS.get(info.status, info.status), "code": info.status, "iters": info.iters,
+           "tau0": info.tau0, "tau": info.tau, "true_res": info.true_res,
+           "phase_ms": list(info.phase_ms), "phase_launches": list(info.phase_launches)}
+    if record:
+        res["hist"] = hist
+    if record_xr:
+        res["xr"] = xr
+    return x, res
+
+
+def device_divsqrt(a, b):
+    lib = load()
+    a, b = _dev(a), _dev(b)
+    q = torch.empty_like(a)
+    s = torch.empty_like(a)
+    _check(lib.rpk_device_divsqrt(a.numel(), _ptr(a), _ptr(b), _ptr(q), _ptr(s), _stream()), "divsqrt")
+    return q, s
+
+
+def version():
+    return load().rpk_version().decode()

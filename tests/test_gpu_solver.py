@@ -1,0 +1,203 @@
+"""GPU PBiCGStab / p-PBiCGStab (through the C ABI) against the oracle: every
+recorded scalar, every iterate, the iteration count, status and residuals."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import T, H, same, first_diff, say
+from paper_2302_04180_amd import inputs, rpk
+
+pytestmark = pytest.mark.gpu
+VARIANTS = [(0, "std"), (1, "pipelined")]
+
+
+def rhs(orc, M, A, xs):
+    """b = A x* computed by each side's own exact SpMV; they must agree."""
+    bo = orc.exspmv(*A, xs)
+    bg = H(rpk.exspmv(M, T(xs)))
+    assert same(bg, bo)
+    return bo
+
+
+def compare(res_o, x_g, info_g, with_hist=True):
+    assert info_g["status"] == res_o["status"], (info_g["status"], res_o["status"])
+    assert info_g["iters"] == res_o["iters"]
+    assert same(info_g["tau0"], res_o["tau0"]) and same(info_g["tau"], res_o["tau"])
+    assert same(info_g["true_res"], res_o["true_res"])
+    if with_hist:
+        hg, ho = H(info_g["hist"]), res_o["hist"]
+        m = min(len(hg), len(ho))
+        assert same(hg[:m], ho[:m]), first_diff(hg[:m], ho[:m])
+    xg = H(x_g)
+    assert same(xg, res_o["x"]), first_diff(xg, res_o["x"])
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_poisson16_config(orc, variant, vname):
+    A = inputs.poisson7(16)
+    M = rpk.Matrix(*A)
+    xs = inputs.uniform(16 ** 3, 1)
+    b = rhs(orc, M, A, xs)
+    ro = orc.solve(*A, b, tol=1e-8, maxit=500, variant=variant, record=True)
+    say("poisson16", vname, "oracle iters", ro["iters"])
+    for fpe in (4, 1):
+        xg, ig = rpk.solve(M, T(b), tol=1e-8, maxit=500, variant=variant, fpe=fpe, record=True)
+        say("  gpu fpe", fpe, ig["status"], ig["iters"])
+        compare(ro, xg, ig)
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_every_iterate_small(orc, variant, vname):
+    A = inputs.convdiff7(6, (0.9, 0.45, 0.225))
+    M = rpk.Matrix(*A)
+    xs = inputs.uniform(216, 5)
+    b = rhs(orc, M, A, xs)
+    ro = orc.solve(*A, b, tol=1e-12, maxit=200, variant=variant, record=True, record_xr=True)
+    xg, ig = rpk.solve(M, T(b), tol=1e-12, maxit=200, variant=variant, record=True, record_xr=True)
+    compare(ro, xg, ig)
+    k = ro["iters"]
+    assert same(H(ig["xr"])[:k], ro["xr"][:k])
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_tiny_systems(orc, variant, vname):
+    for seed in range(4):
+        A = inputs.tiny_nonsym(5 + seed, 40 + seed)
+        M = rpk.Matrix(*A)
+        b = inputs.uniform(5 + seed, 60 + seed)
+        x0 = inputs.uniform(5 + seed, 80 + seed) * (seed % 2)
+        ro = orc.solve(*A, b, x0=x0, tol=1e-13, maxit=40, variant=variant, record=True, record_xr=True)
+        xg, ig = rpk.solve(M, T(b), x0=T(x0), tol=1e-13, maxit=40, variant=variant, record=True,
+                           record_xr=True)
+        compare(ro, xg, ig)
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_launch_shapes_do_not_change_bits(orc, variant, vname):
+    A = inputs.convdiff7(16, (1.5, 0.75, 0.375))
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, inputs.uniform(4096, 9))
+    ro = orc.solve(*A, b, tol=1e-10, maxit=300, variant=variant, record=True)
+    bt = T(b)
+    for block, grid, fpe, graph in [(64, 1, 4, 0), (256, 5, 8, -1), (1024, 64, 2, 3), (128, 16, 1, 0),
+                                    (512, 8, 4, 7)]:
+        say("shape", vname, block, grid, fpe, graph)
+        xg, ig = rpk.solve(M, bt, tol=1e-10, maxit=300, variant=variant, block=block, grid=grid, fpe=fpe,
+                           graph=graph, record=True)
+        compare(ro, xg, ig)
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_repeatable_and_timing_mode(orc, variant, vname):
+    A = inputs.poisson7(12)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, inputs.uniform(1728, 3))
+    ref = None
+    for rep in range(3):
+        xg, ig = rpk.solve(M, T(b), tol=1e-9, maxit=300, variant=variant, timing=(rep == 2))
+        if ref is None:
+            ref = H(xg)
+        assert same(H(xg), ref)
+    assert sum(ig["phase_launches"]) > 0 and sum(ig["phase_ms"]) > 0
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_diagonal_one_iteration(variant, vname):
+    for n in (1, 9, 1000):
+        A = inputs.diagonal_pow2(n, n)
+        M = rpk.Matrix(*A)
+        b = inputs.uniform(n, n + 1)
+        xg, ig = rpk.solve(M, T(b), tol=1e-12, maxit=10, variant=variant)
+        assert ig["status"] == "OK" and ig["iters"] == 1
+        assert same(H(xg), b / A[2]) and ig["tau"] == 0.0
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_failure_paths(orc, variant, vname):
+    # breakdown: <r0, A M^-1 r0> = 0
+    rp = np.array([0, 2, 3], np.int32)
+    ci = np.array([0, 1, 1], np.int32)
+    v = np.array([1.0, 2.0, -1.0])
+    M = rpk.Matrix(rp, ci, v)
+    xg, ig = rpk.solve(M, T([1.0, 1.0]), tol=1e-12, maxit=10, variant=variant)
+    assert ig["status"] == "BREAKDOWN" and ig["iters"] == 0 and np.all(H(xg) == 0.0)
+    # maxit exhaustion returns the same iterate as the oracle
+    A = inputs.poisson7(8)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, inputs.uniform(512, 4))
+    for m in (0, 1, 3):
+        ro = orc.solve(*A, b, tol=1e-14, maxit=m, variant=variant)
+        xg, ig = rpk.solve(M, T(b), tol=1e-14, maxit=m, variant=variant)
+        assert ig["status"] == "NOT_CONVERGED" and ig["iters"] == m
+        assert same(H(xg), ro["x"])
+    # non-finite right-hand side
+    bb = b.copy()
+    bb[7] = math.inf
+    xg, ig = rpk.solve(M, T(bb), tol=1e-8, maxit=10, variant=variant)
+    assert ig["status"] == "ERR_NONFINITE"
+    # zero right-hand side: nothing to do
+    xg, ig = rpk.solve(M, T(np.zeros(512)), tol=1e-8, maxit=10, variant=variant)
+    assert ig["status"] == "OK" and ig["iters"] == 0
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_symmetric_permutation(orc, variant, vname):
+    N = 10
+    rp, ci, v = inputs.convdiff7(N, (0.6, 0.3, 0.15))
+    n = N ** 3
+    b = orc.exspmv(rp, ci, v, inputs.uniform(n, 21))
+    perm = np.random.default_rng(2).permutation(n)
+    inv = np.argsort(perm)
+    rows = [(inv[ci[rp[perm[k]]:rp[perm[k] + 1]]], v[rp[perm[k]]:rp[perm[k] + 1]]) for k in range(n)]
+    rp2 = np.zeros(n + 1, np.int32)
+    rp2[1:] = np.cumsum([len(c) for c, _ in rows])
+    ci2 = np.concatenate([c for c, _ in rows]).astype(np.int32)
+    v2 = np.concatenate([vv for _, vv in rows])
+    M1, M2 = rpk.Matrix(rp, ci, v), rpk.Matrix(rp2, ci2, v2)
+    x1, i1 = rpk.solve(M1, T(b), tol=1e-10, maxit=300, variant=variant, record=True)
+    x2, i2 = rpk.solve(M2, T(b[perm]), tol=1e-10, maxit=300, variant=variant, record=True)
+    assert i1["iters"] == i2["iters"]
+    assert same(H(i1["hist"]), H(i2["hist"]))
+    assert same(H(x1)[perm], H(x2))
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_full_size_first_iterations(orc, variant, vname):
+    """128^3 Poisson, b = A*1, in the default launch configuration: the first
+    iterations equal the oracle's bit for bit."""
+    A = inputs.poisson7(128)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, np.ones(128 ** 3))
+    ro = orc.solve(*A, b, tol=1e-10, maxit=2, variant=variant, record=True)
+    xg, ig = rpk.solve(M, T(b), tol=1e-10, maxit=2, variant=variant, record=True)
+    compare(ro, xg, ig)
+
+
+def test_conv_diff_96_first_iterations(orc):
+    A = inputs.convdiff7(96)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, np.ones(96 ** 3))
+    ro = orc.solve(*A, b, tol=1e-9, maxit=2, variant=1, record=True)
+    xg, ig = rpk.solve(M, T(b), tol=1e-9, maxit=2, variant=1, record=True)
+    compare(ro, xg, ig)
+
+
+def test_random_banded_first_iterations(orc):
+    A = inputs.random_banded()
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, np.ones(500_000))
+    ro = orc.solve(*A, b, tol=1e-9, maxit=2, variant=1, record=True)
+    xg, ig = rpk.solve(M, T(b), tol=1e-9, maxit=2, variant=1, record=True)
+    compare(ro, xg, ig)
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_plain_twin_converges(variant, vname):
+    A = inputs.poisson7(16)
+    M = rpk.Matrix(*A)
+    xs = inputs.uniform(4096, 1)
+    b = H(rpk.exspmv(M, T(xs)))
+    xg, ig = rpk.solve(M, T(b), tol=1e-8, maxit=500, variant=variant, dots=rpk.PLAIN)
+    assert ig["status"] == "OK" and 30 <= ig["iters"] <= 70
+    assert np.max(np.abs(H(xg) - xs)) < 1e-5
