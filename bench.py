@@ -1,0 +1,168 @@
+"""Benchmark: exact (reproducible) PBiCGStab on the 128^3 7-point Poisson system.
+
+One step = one complete exact PBiCGStab solve (Fig. 2, Jacobi, b = A*1, x0 = 0,
+tol 1e-10 on ||r||/||r0||) on one MI355X through the C ABI, inputs resident in
+HBM.  The reported value is iterations per second over the timed steps.  Beside
+it (outside the timed region): the plain FP64 twin and the pipelined variant on
+the same GPU, the per-kernel times of one instrumented solve (roofline of the
+dominant kernel), and the exact CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact PBiCGStab iters/s at 128^3 Poisson vs plain FP64; batched solves/s + p99"
+HBM_PEAK_GBS = 8000.0
+N_EDGE = 128
+TOL = 1e-10
+MAXIT = 5000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n, nnz):
+    """Bytes each operand of the loop moves once (SpMV: CSR + gathered input +
+    output; dots fused into their producers).  CSR = 12 nnz + 4 (n + 1)."""
+    V = 8 * n
+    csr = 12 * nnz + 4 * (n + 1)
+    return {
+        "std_iteration": 2 * csr + 25 * V,
+        "pipelined_iteration": 2 * csr + 42 * V,
+        # phase B (and D): SpMV over the CSR, gather of p^ (q^), write s (y), read r0 (q)
+        "std_spmv_phase": csr + 3 * V,
+    }
+
+
+def cpu_baseline(A, n_iter):
+    import numpy as np
+
+    import oracle
+    oracle.load()
+    b_host = oracle.exspmv(*A, np.ones(A[0].size - 1))
+    t0 = time.perf_counter()
+    res = oracle.solve(*A, b_host, tol=TOL, maxit=n_iter, variant=0)
+    dt = time.perf_counter() - t0
+    return {"value": res["iters"] / dt, "unit": "iters/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": "first %d iterations (set-up and exit residual included) of the exact standard solve "
+                      "of the same 128^3 system; %.1f s" % (res["iters"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2302_04180_amd import inputs, rpk
+
+    torch.cuda.set_device(0)
+    A = inputs.poisson7(N_EDGE)
+    n, nnz = N_EDGE ** 3, int(A[0][-1])
+    M = rpk.Matrix(*A)
+    b = rpk.exspmv(M, torch.ones(n, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+
+    def solve(variant=rpk.STD, dots=rpk.EXACT, **kw):
+        return rpk.solve(M, b, tol=TOL, maxit=MAXIT, variant=variant, dots=dots, **kw)[1]
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        info = solve()
+        assert info["status"] == "OK", info
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        info = solve()
+        iters += info["iters"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    exact_ips = iters / dt
+    it_exact = info["iters"]
+    log("exact std: %d iterations per solve, %.1f iters/s" % (it_exact, exact_ips))
+
+    # comparisons on the same GPU (outside the timed region)
+    def rate(variant, dots, reps=2):
+        solve(variant, dots)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        k = 0
+        for _ in range(reps):
+            inf = solve(variant, dots)
+            k += inf["iters"]
+        torch.cuda.synchronize()
+        return k / (time.perf_counter() - t), inf
+
+    plain_ips, plain_info = rate(rpk.STD, rpk.PLAIN)
+    pipe_ips, pipe_info = rate(rpk.PIPELINED, rpk.EXACT)
+    pplain_ips, pplain_info = rate(rpk.PIPELINED, rpk.PLAIN)
+    log("plain std %.1f iters/s (%d it); exact pipelined %.1f (%d it); plain pipelined %.1f (%d it)" % (
+        plain_ips, plain_info["iters"], pipe_ips, pipe_info["iters"], pplain_ips, pplain_info["iters"]))
+
+    # per-kernel times of one instrumented exact solve (HIP events on the solve's stream)
+    tinfo = solve(timing=True)
+    names = ["A:S12+S1", "B:S2 SpMV+S3 dot", "C:S4+S5", "D:S6 SpMV+S7 dots", "E:S8+S9+S10/S11 dots"]
+    phase = {}
+    for k, nm in enumerate(names):
+        if tinfo["phase_launches"][k]:
+            phase[nm] = round(1e3 * tinfo["phase_ms"][k] / tinfo["phase_launches"][k], 2)  # us per launch
+    dom = max(range(5), key=lambda k: tinfo["phase_ms"][k])
+    by = algorithmic_bytes(n, nnz)
+    avg_s = tinfo["phase_ms"][dom] / tinfo["phase_launches"][dom] / 1e3
+    dom_bytes = by["std_spmv_phase"] if dom in (1, 3) else None
+    if dom_bytes is None:  # elementwise phases: operands read/written once
+        dom_bytes = {0: 6, 2: 5, 4: 8}[dom] * 8 * n
+    achieved = dom_bytes / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": names[dom], "bytes_per_launch": dom_bytes, "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    result = {
+        "metric": METRIC, "value": round(exact_ips, 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (7-point Poisson generated in-process; b = A*1 by the exact SpMV)",
+        "config": {"workload": "poisson7_128^3_std_exact", "n": n, "nnz": nnz, "rhs": "A*ones", "x0": "zeros",
+                   "tol": TOL, "maxit": MAXIT, "preconditioner": "jacobi", "variant": "standard (Fig. 2)",
+                   "parallelism": "single GPU"},
+        "iterations_per_solve": it_exact,
+        "algorithmic_GBps_iteration": round(exact_ips * by["std_iteration"] / 1e9, 1),
+        "iteration_roofline_frac": round(exact_ips * by["std_iteration"] / 1e9 / HBM_PEAK_GBS, 4),
+        "plain_fp64": {"iters_per_s": round(plain_ips, 2), "iterations": plain_info["iters"]},
+        "exact_over_plain_time_per_iteration": round(plain_ips / exact_ips, 3),
+        "pipelined_exact": {"iters_per_s": round(pipe_ips, 2), "iterations": pipe_info["iters"],
+                            "GBps": round(pipe_ips * by["pipelined_iteration"] / 1e9, 1)},
+        "pipelined_plain": {"iters_per_s": round(pplain_ips, 2), "iterations": pplain_info["iters"]},
+        "phase_us": phase,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(A, args.cpu_iters)
+    else:
+        result["cpu_baseline"] = None
+    M.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
