@@ -35,10 +35,13 @@ def algorithmic_bytes(n, nnz):
     V = 8 * n
     csr = 12 * nnz + 4 * (n + 1)
     return {
+        # reference count: every operand of Fig. 2 / Fig. 3 read once, every output written once
         "std_iteration": 2 * csr + 25 * V,
         "pipelined_iteration": 2 * csr + 42 * V,
-        # phase B (and D): SpMV over the CSR, gather of p^ (q^), write s (y), read r0 (q)
-        "std_spmv_phase": csr + 3 * V,
+        # kernels of the standard loop (each operand once):
+        # A: p s r dinv -> p p^ ; B: CSR + gather p^ + r0 -> s ; C: s r dinv -> q q^
+        # D: CSR + gather q^ + q -> y ; E: x p^ q^ y q r0 -> x r
+        "std_kernel": {0: 6 * V, 1: csr + 3 * V, 3: 5 * V, 4: csr + 3 * V, 6: 8 * V},
     }
 
 
@@ -120,17 +123,16 @@ def main():
 
     # per-kernel times of one instrumented exact solve (HIP events on the solve's stream)
     tinfo = solve(timing=True)
-    names = ["A:S12+S1", "B:S2 SpMV+S3 dot", "C:S4+S5", "D:S6 SpMV+S7 dots", "E:S8+S9+S10/S11 dots"]
+    names = ["A: S12+S1", "B: S2 SpMV, S3 partial", "finish alpha", "C: S4+S5", "D: S6 SpMV, S7 partials",
+             "finish omega", "E: S8+S9, S10/S11 partials", "finish beta/tau"]
     phase = {}
     for k, nm in enumerate(names):
         if tinfo["phase_launches"][k]:
             phase[nm] = round(1e3 * tinfo["phase_ms"][k] / tinfo["phase_launches"][k], 2)  # us per launch
-    dom = max(range(5), key=lambda k: tinfo["phase_ms"][k])
     by = algorithmic_bytes(n, nnz)
+    dom = max((0, 1, 3, 4, 6), key=lambda k: tinfo["phase_ms"][k])
     avg_s = tinfo["phase_ms"][dom] / tinfo["phase_launches"][dom] / 1e3
-    dom_bytes = by["std_spmv_phase"] if dom in (1, 3) else None
-    if dom_bytes is None:  # elementwise phases: operands read/written once
-        dom_bytes = {0: 6, 2: 5, 4: 8}[dom] * 8 * n
+    dom_bytes = by["std_kernel"][dom]
     achieved = dom_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

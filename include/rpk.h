@@ -63,7 +63,7 @@ typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1 } rpk_dotmode;
 
 /* Launch shape.  Results of the exact mode do not depend on it. */
 typedef struct {
-  int32_t block;  /* workgroup size, a multiple of 64 in [64, 1024]; 0 = 256 */
+  int32_t block;  /* workgroup size, a multiple of 64 in [64, 1024]; 0 = 512 */
   int32_t grid;   /* workgroups of the streaming kernels, >= 1; 0 = automatic */
   int32_t fpe;    /* FPE length 1, 2, 4 or 8 (1 sends almost every term to the
                      long accumulator); 0 = 4 */
@@ -83,7 +83,7 @@ typedef struct {
                           iteration, or NULL                                 */
 } rpk_opts;
 
-#define RPK_NPHASE 8
+#define RPK_NPHASE 12
 typedef struct {
   int32_t status;      /* rpk_status of the solve                             */
   int32_t iters;       /* completed iterations                                */

@@ -74,6 +74,22 @@ __device__ __forceinline__ double fpe_add(Fpe<N>& f, double x) {
   return x;
 }
 
+// Same cascade starting at component S: used for the twoprod error terms,
+// which are too small to change the leading component.  Any start level keeps
+// the sum exact; the choice only shortens the cascade.
+template <int N, int S>
+__device__ __forceinline__ double fpe_add_from(Fpe<N>& f, double x) {
+#pragma unroll
+  for (int k = S; k < N; ++k) {
+    if (x == 0.0) break;
+    double r, s;
+    two_sum(f.c[k], x, r, s);
+    f.c[k] = r;
+    x = s;
+  }
+  return x;
+}
+
 // Correct rounding (nearest, ties to even) of the exact sum of an FPE whose sum
 // is below 2^1022 in magnitude.
 //  1. Grow-expansion (Shewchuk 1997, Thm. 10): inserting the components one by
@@ -88,6 +104,15 @@ __device__ __forceinline__ double fpe_add(Fpe<N>& f, double x) {
 //  An exact zero gives +0.0.
 template <int N>
 __device__ __forceinline__ double fpe_round(const Fpe<N>& f) {
+  // two non-zero components at most: IEEE addition is already the correctly
+  // rounded sum (an exact zero sum is returned as +0)
+  bool rest = false;
+#pragma unroll
+  for (int k = 2; k < N; ++k) rest |= (f.c[k] != 0.0);
+  if (!rest) {
+    const double r = (N > 1) ? f.c[0] + f.c[N > 1 ? 1 : 0] : f.c[0];
+    return (r == 0.0) ? 0.0 : r;
+  }
   double h[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -196,54 +221,60 @@ __device__ __forceinline__ void sa_add_prod(long long* acc, double a, double b) 
   sa_add_int(acc, na != nb, __umul64hi(ma, mb), ma * mb, ea + eb);
 }
 
-// Single thread: rewrite the digits so that 0..SA_D-2 lie in [0, 2^32) and the
-// top digit carries the (small) signed remainder.  Same value.
-__device__ inline void sa_normalize(long long* acc) {
+// ---------------------------------------------------------------------------
+// Rounding of a digit window.  w[k] (k = lo..hi) holds digit base+k of the
+// global grid as a signed 64-bit value (carries not propagated); digits outside
+// [lo, hi] are zero.  The caller leaves headroom so that the normalised value
+// fits below digit hi+1 with digit hi as its (small) signed top.  One thread;
+// overwrites w[lo..hi].  Exact zero -> +0.0; a non-zero value below 2^-1075
+// rounds to a zero of its own sign; overflow -> +-inf.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long win_digit(const long long* w, int lo, int hi, int base, int dabs) {
+  const int k = dabs - base;
+  return (k >= lo && k <= hi) ? w[k] : 0ll;
+}
+
+__device__ inline double window_round(long long* w, int lo, int hi, int base) {
   long long carry = 0;
-  for (int k = 0; k < SA_D - 1; ++k) {
-    const long long v = acc[k] + carry;
-    acc[k] = v & 0xffffffffll;
+  for (int k = lo; k < hi; ++k) {
+    const long long v = w[k] + carry;
+    w[k] = v & 0xffffffffll;
     carry = v >> 32;
   }
-  acc[SA_D - 1] += carry;
-}
-
-__device__ inline int sa_bit(const long long* acc, int i) {
-  return (int)((acc[i >> 5] >> (i & 31)) & 1);
-}
-
-// Single thread: round the accumulator to nearest-even (overwrites it).
-// Exact zero -> +0.0; a non-zero value below 2^-1075 -> signed zero.
-__device__ inline double sa_round(long long* acc) {
-  sa_normalize(acc);
-  long long top = acc[SA_D - 1];
+  long long top = w[hi] + carry;
   const bool neg = top < 0;
-  if (neg) {  // magnitude by two's complement negation over the digits
+  if (neg) {  // magnitude by two's complement negation over the window
     long long borrow = 0;
-    for (int k = 0; k < SA_D - 1; ++k) {
-      const long long v = -acc[k] - borrow;
-      acc[k] = v & 0xffffffffll;
+    for (int k = lo; k < hi; ++k) {
+      const long long v = -w[k] - borrow;
+      w[k] = v & 0xffffffffll;
       borrow = (v < 0) ? 1 : 0;
     }
     top = -top - borrow;
   }
-  acc[SA_D - 1] = top;
-  int t = SA_D - 1;
-  while (t >= 0 && acc[t] == 0) --t;
-  if (t < 0) return 0.0;
-  const int lead = 32 * t + (63 - __clzll((unsigned long long)acc[t]));
-  const int low = (lead - 52 > SA_SUB_BIT) ? lead - 52 : SA_SUB_BIT;
+  w[hi] = top;
+  int t = hi;
+  while (t >= lo && w[t] == 0) --t;
+  if (t < lo) return 0.0;
+  const int lead = 32 * (base + t) + (63 - __clzll((unsigned long long)w[t]));  // grid bit of the leading 1
+  const int low = (lead - 52 > SA_SUB_BIT) ? lead - 52 : SA_SUB_BIT;            // grid bit of the last kept bit
+  const int nbits = lead - low + 1;                                              // <= 53 (may be <= 0)
   unsigned long long mant = 0;
-  for (int i = lead; i >= low; --i) mant = (mant << 1) | (unsigned long long)sa_bit(acc, i);
-  const int guard = sa_bit(acc, low - 1);
-  int sticky = 0;
-  {
-    const int g = low - 1;  // bits strictly below g
-    const int gd = g >> 5;
-    if (acc[gd] & ((1ll << (g & 31)) - 1)) sticky = 1;
-    for (int k = 0; k < gd && !sticky; ++k)
-      if (acc[k] != 0) sticky = 1;
+  if (nbits > 0) {
+    const int a = low >> 5, sh = low & 31;
+    const unsigned long long x = (unsigned long long)win_digit(w, lo, hi, base, a) |
+                                 ((unsigned long long)win_digit(w, lo, hi, base, a + 1) << 32);
+    mant = x >> sh;
+    if (64 - sh < nbits) mant |= (unsigned long long)win_digit(w, lo, hi, base, a + 2) << (64 - sh);
+    mant &= (nbits >= 64) ? ~0ull : ((1ull << nbits) - 1ull);
   }
+  const int g = low - 1;  // guard bit
+  const int gd = g >> 5, gb = g & 31;
+  const unsigned long long gdig = (unsigned long long)win_digit(w, lo, hi, base, gd);
+  const int guard = (int)((gdig >> gb) & 1ull);
+  int sticky = (gdig & ((1ull << gb) - 1ull)) != 0ull;
+  for (int k = lo; k <= hi && !sticky; ++k)
+    if (base + k < gd && w[k] != 0) sticky = 1;
   if (guard && (sticky || (mant & 1ull))) mant += 1ull;
   // value = mant * 2^q, q = low + SA_LSB >= -1074; IEEE bits = ((q + 1074) << 52) + mant
   const long long q = (long long)low + SA_LSB;
@@ -251,6 +282,137 @@ __device__ inline double sa_round(long long* acc) {
   if (bits >= 0x7ff0000000000000ull) bits = 0x7ff0000000000000ull;
   if (neg) bits |= 0x8000000000000000ull;
   return __longlong_as_double((long long)bits);
+}
+
+// Same rounding for a window of W digits copied into registers first (one thread;
+// static indexing only, so no memory latency in the carry chain).  The window's
+// top two digits must be zero on entry (carry room).
+template <int W>
+__device__ inline double window_round_reg(const long long* win, int base) {
+  long long d[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) d[k] = win[k];
+  long long carry = 0;
+#pragma unroll
+  for (int k = 0; k < W - 1; ++k) {
+    const long long v = d[k] + carry;
+    d[k] = v & 0xffffffffll;
+    carry = v >> 32;
+  }
+  long long top = d[W - 1] + carry;
+  const bool neg = top < 0;
+  if (neg) {
+    long long borrow = 0;
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) {
+      const long long v = -d[k] - borrow;
+      d[k] = v & 0xffffffffll;
+      borrow = (v < 0) ? 1 : 0;
+    }
+    top = -top - borrow;
+  }
+  d[W - 1] = top;
+  int t = -1;
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (d[k] != 0) t = k;
+  if (t < 0) return 0.0;
+  long long dt = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (k == t) dt = d[k];
+  const int lead = 32 * (base + t) + (63 - __clzll((unsigned long long)dt));
+  const int low = (lead - 52 > SA_SUB_BIT) ? lead - 52 : SA_SUB_BIT;
+  const int nbits = lead - low + 1;
+  const int a = (low >> 5) - base, sh = low & 31;  // window index of the digit holding bit `low`
+  unsigned long long x0 = 0, x1 = 0, x2 = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    x0 = (k == a) ? (unsigned long long)d[k] : x0;
+    x1 = (k == a + 1) ? (unsigned long long)d[k] : x1;
+    x2 = (k == a + 2) ? (unsigned long long)d[k] : x2;
+  }
+  unsigned long long mant = 0;
+  if (nbits > 0) {
+    mant = (x0 | (x1 << 32)) >> sh;
+    if (64 - sh < nbits) mant |= x2 << (64 - sh);
+    mant &= (1ull << nbits) - 1ull;
+  }
+  const int g = low - 1;
+  const int gi = (g >> 5) - base, gb = g & 31;
+  unsigned long long gdig = 0;
+  int sticky = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    gdig = (k == gi) ? (unsigned long long)d[k] : gdig;
+    sticky |= (k < gi && d[k] != 0) ? 1 : 0;
+  }
+  const int guard = (int)((gdig >> gb) & 1ull);
+  sticky |= (gdig & ((1ull << gb) - 1ull)) != 0ull;
+  if (guard && (sticky || (mant & 1ull))) mant += 1ull;
+  const long long q = (long long)low + SA_LSB;
+  unsigned long long bits = ((unsigned long long)(q + 1074) << 52) + mant;
+  if (bits >= 0x7ff0000000000000ull) bits = 0x7ff0000000000000ull;
+  if (neg) bits |= 0x8000000000000000ull;
+  return __longlong_as_double((long long)bits);
+}
+
+// Whole wavefront: lowest / highest non-zero digit of a[0..len) (hi = -1 if none).
+__device__ inline void wave_digit_range(const long long* a, int len, int& lo, int& hi) {
+  const int lane = threadIdx.x & 63;
+  lo = len;
+  hi = -1;
+  for (int base = 0; base < len; base += 64) {
+    const int k = base + lane;
+    const unsigned long long m = __ballot(k < len && a[k] != 0);
+    if (m) {
+      const int l = base + (__ffsll((long long)m) - 1);
+      const int h = base + (63 - __clzll((long long)m));
+      lo = (l < lo) ? l : lo;
+      hi = h;
+    }
+  }
+}
+
+// Whole wavefront: round the long accumulator `acc` (SA_D digits, overwritten).
+__device__ inline double sa_round_wave(long long* acc) {
+  int lo, hi;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  wave_digit_range(acc, SA_D, lo, hi);
+  double r = 0.0;
+  if ((threadIdx.x & 63) == 0 && hi >= 0) r = window_round(acc, lo, (hi + 2 < SA_D) ? hi + 2 : SA_D - 1, 0);
+  return __shfl(r, 0, 64);
+}
+
+// Whole wavefront: rewrite acc so that its non-zero digits below the top one lie
+// in [0, 2^32) (same value); returns the digit range [lo, hi] that may be non-zero.
+__device__ inline void sa_normalize_wave(long long* acc, int& lo, int& hi) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  wave_digit_range(acc, SA_D, lo, hi);
+  if (hi < 0) return;
+  hi = (hi + 2 < SA_D) ? hi + 2 : SA_D - 1;
+  if ((threadIdx.x & 63) == 0) {
+    long long carry = 0;
+    for (int k = lo; k < hi; ++k) {
+      const long long v = acc[k] + carry;
+      acc[k] = v & 0xffffffffll;
+      carry = v >> 32;
+    }
+    acc[hi] += carry;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// grid digit holding the leading bit of a non-zero finite double
+__device__ __forceinline__ int top_digit(double x) {
+  bool neg;
+  unsigned long long m;
+  int e;
+  decode(x, neg, m, e);
+  return (e - SA_LSB + (63 - __clzll((long long)m))) >> 5;
 }
 
 // ---------------------------------------------------------------------------
@@ -267,7 +429,7 @@ __device__ __forceinline__ void acc_prod(Fpe<N>& f, double a, double b, long lon
   if (ap >= kProdLo && ap < kProdHi) {
     const double e = fma(a, b, -p);
     const double l1 = fpe_add(f, p);
-    const double l2 = fpe_add(f, e);
+    const double l2 = fpe_add_from<N, (N > 1 ? 1 : 0)>(f, e);
     if (l1 != 0.0 || l2 != 0.0) {
       sa_add_double(sa, l1);
       sa_add_double(sa, l2);
@@ -281,52 +443,6 @@ __device__ __forceinline__ void acc_prod(Fpe<N>& f, double a, double b, long lon
       atomicOr(flag, F_SA);
     }
   }
-}
-
-// Merge FPE g into f (exact); leftovers to the long accumulator.
-template <int N>
-__device__ __forceinline__ void fpe_merge(Fpe<N>& f, const Fpe<N>& g, long long* sa, int* flag) {
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const double l = fpe_add(f, g.c[k]);
-    if (l != 0.0) {
-      sa_add_double(sa, l);
-      atomicOr(flag, F_SA);
-    }
-  }
-}
-
-// Tree reduction inside a wavefront: lane 0 ends with the sum of all lanes.
-// Only receiving lanes merge, so every leftover is deposited exactly once.
-template <int N>
-__device__ __forceinline__ void fpe_wave_reduce(Fpe<N>& f, long long* sa, int* flag, int width = 64) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    if (off < width) {
-      Fpe<N> o;
-#pragma unroll
-      for (int k = 0; k < N; ++k) o.c[k] = __shfl_down(f.c[k], off, 64);
-      if (lane < off) fpe_merge(f, o, sa, flag);
-    }
-  }
-}
-
-// Block reduction; thread 0 ends with the block sum.  wbuf: >= blockDim/64 FPEs in LDS.
-template <int N>
-__device__ __forceinline__ void fpe_block_reduce(Fpe<N>& f, Fpe<N>* wbuf, long long* sa, int* flag) {
-  fpe_wave_reduce(f, sa, flag);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  if (nw > 1) {
-    if (lane == 0) wbuf[w] = f;
-    __syncthreads();
-    if (w == 0) {
-      if (lane < nw) f = wbuf[lane];
-      else fpe_zero(f);
-      fpe_wave_reduce(f, sa, flag, nw);
-    }
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------

@@ -10,10 +10,13 @@ static rpk_status launch(K kernel, int grid, int block, size_t shm, hipStream_t 
   return hipGetLastError() == hipSuccess ? RPK_OK : RPK_ERR_HIP;
 }
 
+constexpr int FB = 1024;  // workgroup size of the one-workgroup finishing kernels
+
 template <int N>
 rpk_status Kern<N>::dot(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* out,
                         Red red) {
-  return launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, out, red);
+  RET_IF(launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, red));
+  return launch(k_dot_finish<N>, 1, FB, shm_bytes(N, 1, false, FB), s, out, red);
 }
 
 template <int N>
@@ -23,7 +26,10 @@ rpk_status Kern<N>::spmv(int G, int B, hipStream_t s, Csr A, const double* x, do
 
 template <int N>
 rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
-  if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+  if (variant == RPK_STD) {
+    RET_IF(launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+    return launch(k_finish<N, 1, FIN_ENTRY>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
+  }
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   return launch(k_pipe_init3<N>, G + 1, B, shm_bytes(N, 2, true, B), s, A, V, red);
@@ -31,7 +37,8 @@ rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V
 
 template <int N>
 rpk_status Kern<N>::resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
-  return launch(k_resid<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+  RET_IF(launch(k_resid<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+  return launch(k_finish<N, 1, FIN_RESID>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
 }
 
 template <int N>
@@ -40,9 +47,12 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
     switch (ph) {
       case 0: return launch(k_std_A<N>, G, B, 0, s, A, V);
       case 1: return launch(k_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 2: return launch(k_std_C<N>, G, B, 0, s, A, V);
-      case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
-      default: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      case 2: return launch(k_finish<N, 1, FIN_ALPHA>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
+      case 3: return launch(k_std_C<N>, G, B, 0, s, A, V);
+      case 4: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
+      case 5: return launch(k_finish<N, 2, FIN_OMEGA>, 1, FB, shm_bytes(N, 2, false, FB), s, V, red);
+      case 6: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      default: return launch(k_finish<N, 2, FIN_BETA>, 1, FB, shm_bytes(N, 2, false, FB), s, V, red);
     }
   }
   switch (ph) {

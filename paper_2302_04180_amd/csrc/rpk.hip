@@ -22,10 +22,14 @@ using namespace rpk;
 
 struct rpk_matrix {
   int64_t n = 0, nnz = 0;
-  int* rp = nullptr;
+  int* rp = nullptr;  // CSR as given (validated), kept for reference
   int* ci = nullptr;
   double* v = nullptr;
   double* dinv = nullptr;
+  int nslices = 0;    // SELL-64 copy used by the kernels
+  long long* sptr = nullptr;
+  int* scol = nullptr;
+  double* sval = nullptr;
 };
 
 namespace {
@@ -40,7 +44,7 @@ struct Cfg {
 };
 
 rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
-  c->block = (L && L->block) ? L->block : 256;
+  c->block = (L && L->block) ? L->block : 512;
   c->fpe = (L && L->fpe) ? L->fpe : 4;
   c->graph = L ? L->graph : 0;
   if (c->block < 64 || c->block > 1024 || (c->block % 64) != 0) return RPK_ERR_ARG;
@@ -50,9 +54,11 @@ rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
     if (L->grid < 1 || L->grid > 65535) return RPK_ERR_ARG;
     c->grid = L->grid;
   } else {
+    // about two workgroups per CU of 256 CUs: few enough records for the
+    // finishing workgroup, enough waves in flight for the streams
     int64_t need = (n + c->block - 1) / c->block;
     if (need < 1) need = 1;
-    if (need > 1024) need = 1024;
+    if (need > 512) need = 512;
     if (need >= 8) need &= ~7ll;
     c->grid = (int)need;
   }
@@ -78,7 +84,7 @@ Layout layout(int grid, int64_t n, int nvec) {
   l.gsa = off;
   off += up((size_t)MAX_DOTS * SA_D * sizeof(long long));
   l.partials = off;
-  off += up((size_t)MAX_DOTS * 8 * grid * sizeof(double));
+  off += up((size_t)MAX_DOTS * REC * grid * sizeof(long long));
   l.vecs = off;
   off += (size_t)nvec * up((size_t)n * sizeof(double));
   l.total = off;
@@ -97,7 +103,7 @@ Red make_red(char* ws, const Layout& l, int grid) {
 
 int nvec_of(int variant) { return variant == RPK_STD ? 8 : 16; }
 
-Csr csr_of(const rpk_matrix* A) { return Csr{A->rp, A->ci, A->v, A->dinv, (int)A->n}; }
+Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n}; }
 
 template <template <int> class F, typename... Args>
 rpk_status by_fpe(int N, Args&&... args) {
@@ -193,7 +199,42 @@ static void free_matrix(rpk_matrix* A) {
   if (A->ci) (void)hipFree(A->ci);
   if (A->v) (void)hipFree(A->v);
   if (A->dinv) (void)hipFree(A->dinv);
+  if (A->sptr) (void)hipFree(A->sptr);
+  if (A->scol) (void)hipFree(A->scol);
+  if (A->sval) (void)hipFree(A->sval);
   delete A;
+}
+
+// SELL-64 copy of the validated CSR (slice widths, prefix sum, padded fill)
+static rpk_status build_sell(rpk_matrix* A, hipStream_t s) {
+  const int n = (int)A->n;
+  const int ns = (n + 63) / 64;
+  A->nslices = ns;
+  int* width = nullptr;
+  if (hipMalloc((void**)&width, (size_t)ns * sizeof(int)) != hipSuccess) return RPK_ERR_NOMEM;
+  if (hipMalloc((void**)&A->sptr, (size_t)(ns + 1) * sizeof(long long)) != hipSuccess) {
+    (void)hipFree(width);
+    return RPK_ERR_NOMEM;
+  }
+  rpk_status st = RPK_OK;
+  long long total = 0;
+  do {
+    hipLaunchKernelGGL(k_slice_width, dim3((ns + 255) / 256), dim3(256), 0, s, A->rp, n, ns, width);
+    if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
+    hipLaunchKernelGGL(k_slice_scan, dim3(1), dim3(1024), 0, s, width, ns, A->sptr);
+    if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hipMemcpyAsync(&total, A->sptr + ns, sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    const size_t cnt = (size_t)(total > 0 ? total : 1);
+    if (hipMalloc((void**)&A->scol, cnt * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&A->sval, cnt * sizeof(double)) != hipSuccess) { st = RPK_ERR_NOMEM; break; }
+    const long long rows = (long long)ns * 64;
+    hipLaunchKernelGGL(k_fill_sell, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, A->rp, A->ci, A->v, n,
+                       ns, (const long long*)A->sptr, A->scol, A->sval);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+  } while (0);
+  (void)hipFree(width);
+  return st;
 }
 
 static rpk_status create_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
@@ -233,7 +274,8 @@ static rpk_status create_impl(int64_t n, int64_t nnz, const int32_t* rp, const i
     else if (hflags[1] & CHK_DIAG) st = RPK_ERR_ZERO_DIAG;
   } while (0);
   (void)hipFree(flags);
-  return st;
+  if (st != RPK_OK) return st;
+  return build_sell(A, s);
 }
 
 rpk_status rpk_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -354,7 +396,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   const int variant = o->variant;
   const int N = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
   const int G = c.grid, B = c.block;
-  const int nph = (variant == RPK_STD) ? 5 : 4;
+  const int nph = (variant == RPK_STD) ? 8 : 4;
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
@@ -399,8 +441,8 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
       if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }
       float ms = 0.f;
       hipEventElapsedTime(&ms, ev[0], ev[1]);
-      info->phase_ms[6] += ms;
-      info->phase_launches[6] += 1;
+      info->phase_ms[8] += ms;
+      info->phase_launches[8] += 1;
     }
     if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
@@ -469,8 +511,8 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
       if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }
       float ms = 0.f;
       hipEventElapsedTime(&ms, ev[0], ev[1]);
-      info->phase_ms[7] += ms;
-      info->phase_launches[7] += 1;
+      info->phase_ms[9] += ms;
+      info->phase_launches[9] += 1;
     }
     if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }

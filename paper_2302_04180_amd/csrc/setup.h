@@ -42,6 +42,61 @@ __global__ void k_setup_rows(const int* rp, const int* ci, const double* v, int 
   if (fl) atomicOr(flags, fl);
 }
 
+// SELL-64 construction (see Csr): width of each 64-row slice ...
+__global__ void k_slice_width(const int* rp, int n, int nslices, int* width) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  int w = 0;
+  const int r1 = (s * 64 + 64 < n) ? s * 64 + 64 : n;
+  for (int r = s * 64; r < r1; ++r) {
+    const int len = rp[r + 1] - rp[r];
+    w = (len > w) ? len : w;
+  }
+  width[s] = w;
+}
+
+// ... exclusive prefix sum of 64*width into sptr[0..nslices] (one workgroup of 1024) ...
+__global__ void __launch_bounds__(1024) k_slice_scan(const int* width, int nslices, long long* sptr) {
+  __shared__ long long buf[1024];
+  long long carry = 0;
+  for (int base = 0; base < nslices; base += 1024) {
+    const int i = base + threadIdx.x;
+    buf[threadIdx.x] = (i < nslices) ? 64ll * width[i] : 0ll;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const long long v = (threadIdx.x >= (unsigned)d) ? buf[threadIdx.x - d] : 0ll;
+      __syncthreads();
+      buf[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (i < nslices) sptr[i + 1] = carry + buf[threadIdx.x];
+    carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sptr[0] = 0;
+}
+
+// ... and the entries, padded with (0, own row); rows past n point at column 0.
+__global__ void k_fill_sell(const int* rp, const int* ci, const double* v, int n, int nslices, const long long* sptr,
+                            int* scol, double* sval) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (long long)nslices * 64) return;
+  const int s = (int)(r >> 6), lane = (int)(r & 63);
+  const long long off = sptr[s];
+  const int w = (int)((sptr[s + 1] - off) >> 6);
+  const int k0 = (r < n) ? rp[r] : 0, len = (r < n) ? rp[r + 1] - rp[r] : 0;
+  for (int j = 0; j < w; ++j) {
+    const long long at = off + 64ll * j + lane;
+    if (j < len) {
+      scol[at] = ci[k0 + j];
+      sval[at] = v[k0 + j];
+    } else {
+      scol[at] = (r < n) ? (int)r : 0;
+      sval[at] = 0.0;
+    }
+  }
+}
+
 __global__ void k_fill(double* p, long long n, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;

@@ -1,11 +1,16 @@
 // solver.h -- fused phase kernels of PBiCGStab (Fig. 2) and p-PBiCGStab (Fig. 3).
 //
-// Standard loop, five kernels per iteration:
-//   A: S12 (from the second iteration on) + S1        p, p^ update
-//   B: S2 SpMV + S3 dot <r0,s>; last block: alpha
-//   C: S4 + S5                                         q, q^
-//   D: S6 SpMV + S7 dots <q,y>, <y,y>; last block: omega
-//   E: S8 + S9 + S10/S11 dots <r0,r>, <r,r>; last block: tau, stop test, beta
+// Standard loop, five streaming kernels per iteration; each reduction point is
+// followed by a one-workgroup kernel that rounds the dot products and takes the
+// scalar step (no grid-wide fences: on gfx950 an agent-scope release writes
+// back the XCD's L2, which made a last-block-finishes scheme cost more than the
+// kernels).  Recomputing p^ / q^ inside the SpMV gathers instead of storing
+// them was measured slower: it multiplies the gathered vectors by 3-4.
+//   A: S12 (from the second iteration on) + S1
+//   B: S2 SpMV (gathers p^) + S3 partials         -> finish: alpha
+//   C: S4 + S5
+//   D: S6 SpMV (gathers q^) + S7 partials         -> finish: omega
+//   E: S8 + S9, S10/S11 partials                  -> finish: tau, stop test, beta
 // Pipelined loop, four kernels per iteration; each reduction is finished by one
 // extra workgroup of the following SpMV kernel, so it overlaps that SpMV (the
 // single-GPU counterpart of the Iallreduce/Wait pairs of Sec. 4.2):
@@ -23,7 +28,7 @@ namespace rpk {
 __device__ __forceinline__ double qnan() { return __longlong_as_double(0x7ff8000000000000ll); }
 
 struct Vecs {
-  // standard: r0 r p ph s q qh y ; pipelined adds rh w wh t sh z zh v
+  // standard: r0 r p ph s q qh y ; pipelined: r0 r ph s q qh y rh w wh t sh z zh v
   double *r0, *r, *p, *ph, *s, *q, *qh, *y;
   double *rh, *w, *wh, *t, *sh, *z, *zh, *v;
   double* x;
@@ -47,13 +52,28 @@ __device__ __forceinline__ void record_xr(const Vecs& V, int iter, int n, int ro
 // ---------------------------------------------------------------------------
 // scalar steps (thread 0 of the finishing workgroup)
 // ---------------------------------------------------------------------------
-__device__ inline void stop(State* st, int status) {
+// field-wise copies keep a local State in registers (a whole-struct copy is
+// lowered to a memcpy that puts it in private memory)
+__device__ __forceinline__ void state_load(State& d, const State* s) {
+  d.alpha = s->alpha; d.omega = s->omega; d.beta = s->beta; d.rho = s->rho;
+  d.tau = s->tau; d.tau0 = s->tau0; d.tol = s->tol; d.true_res = s->true_res;
+  d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
+  d.variant = s->variant; d.pad0 = 0; d.pad1 = 0; d.pad2 = 0;
+}
+
+__device__ __forceinline__ void state_store(State* d, const State& s) {
+  d->alpha = s.alpha; d->omega = s.omega; d->beta = s.beta; d->rho = s.rho;
+  d->tau = s.tau; d->tau0 = s.tau0; d->tol = s.tol; d->true_res = s.true_res;
+  d->iter = s.iter; d->maxit = s.maxit; d->done = s.done; d->status = s.status;
+}
+
+__device__ __forceinline__ void stop(State* st, int status) {
   st->status = status;
   st->done = 1;
 }
 
 // r0 := b - A x0, tau0 := ||r0|| ; loop entry test
-__device__ inline void step_entry(State* st, double rho) {
+__device__ __forceinline__ void step_entry(State* st, double rho) {
   if (isnan(rho)) {
     st->tau0 = st->tau = qnan();
     stop(st, ST_NONFINITE);
@@ -65,14 +85,14 @@ __device__ inline void step_entry(State* st, double rho) {
   if (st->tau0 == 0.0) stop(st, ST_OK);
 }
 
-__device__ inline void step_loop_entry(State* st) {
+__device__ __forceinline__ void step_loop_entry(State* st) {
   if (st->done) return;
   if (st->tau / st->tau0 <= st->tol) stop(st, ST_OK);
   else if (st->maxit <= 0) stop(st, ST_NOT_CONVERGED);
 }
 
 // S3: alpha = rho / <r0, s>
-__device__ inline void step_std_alpha(State* st, double* h, double sigma) {
+__device__ __forceinline__ void step_std_alpha(State* st, double* h, double sigma) {
   if (h) h[0] = sigma;
   if (isnan(sigma)) return stop(st, ST_NONFINITE);
   if (sigma == 0.0) return stop(st, ST_BREAKDOWN);
@@ -81,7 +101,7 @@ __device__ inline void step_std_alpha(State* st, double* h, double sigma) {
 }
 
 // S7 / S11: omega = <q,y> / <y,y>  (0 when <y,y> = 0)
-__device__ inline void step_omega(State* st, double* h, double theta, double phi, int at) {
+__device__ __forceinline__ void step_omega(State* st, double* h, double theta, double phi, int at) {
   if (h) {
     h[at] = theta;
     h[at + 1] = phi;
@@ -92,7 +112,7 @@ __device__ inline void step_omega(State* st, double* h, double theta, double phi
 }
 
 // S10 + S11 and the stop test; beta for S12
-__device__ inline void step_std_beta(State* st, double* h, double rho_new, double gamma) {
+__device__ __forceinline__ void step_std_beta(State* st, double* h, double rho_new, double gamma) {
   if (h) {
     h[5] = rho_new;
     h[6] = gamma;
@@ -110,7 +130,7 @@ __device__ inline void step_std_beta(State* st, double* h, double rho_new, doubl
 }
 
 // pipelined set-up: alpha0 = rho / <r0, w>
-__device__ inline void step_pipe_entry(State* st, double rho, double mu) {
+__device__ __forceinline__ void step_pipe_entry(State* st, double rho, double mu) {
   step_entry(st, rho);
   if (st->done) return;
   if (isnan(mu)) return stop(st, ST_NONFINITE);
@@ -122,7 +142,7 @@ __device__ inline void step_pipe_entry(State* st, double rho, double mu) {
 }
 
 // S19
-__device__ inline void step_pipe_s19(State* st, double* h, const double* d) {
+__device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double* d) {
   const double rho_new = d[0], mu_new = d[1], vs = d[2], zeta = d[3], gamma = d[4];
   if (h)
     for (int k = 0; k < 5; ++k) h[3 + k] = d[k];
@@ -150,6 +170,7 @@ __device__ inline void step_pipe_s19(State* st, double* h, const double* d) {
 // ---------------------------------------------------------------------------
 // standard loop
 // ---------------------------------------------------------------------------
+// r0 := b - A x0, p := r0 ; partial <r0, r0> (slot 0)
 template <int N>
 __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
@@ -171,12 +192,7 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[1])) return;
-  block_finalize<N, 1>(s, red, 0);
-  if (threadIdx.x == 0) {
-    step_entry(V.st, s.res[0]);
-    step_loop_entry(V.st);
-  }
+  block_publish<N, 1>(d, s, red, 0);
 }
 
 // A: S12 (iterations after the first) and S1
@@ -188,17 +204,36 @@ __global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
   const double beta = st->beta, omega = st->omega;
   const int L = xcd_block(blockIdx.x, gridDim.x);
   const Range R = block_rows(A.n, L, gridDim.x);
-  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    double p = V.p[i];
+  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+    const int i1 = i0 + blockDim.x;
+    const bool two = i1 < R.hi;
+    const int j1 = two ? i1 : i0;
+    double p[2], s[2], r[2], d[2];
+    p[0] = V.p[i0];
+    p[1] = V.p[j1];
+    d[0] = A.dinv[i0];
+    d[1] = A.dinv[j1];
     if (upd) {
-      p = fma(beta, fma(-omega, V.s[i], p), V.r[i]);
-      V.p[i] = p;
+      s[0] = V.s[i0];
+      s[1] = V.s[j1];
+      r[0] = V.r[i0];
+      r[1] = V.r[j1];
     }
-    V.ph[i] = A.dinv[i] * p;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const int i = u ? i1 : i0;
+      double pv = p[u];
+      if (upd) {
+        pv = fma(beta, fma(-omega, s[u], pv), r[u]);  // S12
+        V.p[i] = pv;
+      }
+      V.ph[i] = d[u] * pv;  // S1
+    }
   }
 }
 
-// B: S2 + S3
+// B: S2 + S3 partial
 template <int N>
 __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
@@ -212,15 +247,14 @@ __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
     const int i = base + threadIdx.x;
     const bool ok = i < R.hi;
+    const double r0 = ok ? V.r0[i] : 0.0;
     const double si = rows_wave<N>(A, V.ph, i, ok, s.wsa);
     if (ok) {
       V.s[i] = si;
-      d[0].add(V.r0[i], si, s.sa, &s.flag[0]);
+      d[0].add(r0, si, s.sa, &s.flag[0]);
     }
   }
-  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[2])) return;
-  block_finalize<N, 1>(s, red, 0);
-  if (threadIdx.x == 0) step_std_alpha(V.st, hist_row(V, V.st->iter), s.res[0]);
+  block_publish<N, 1>(d, s, red, 0);
 }
 
 // C: S4 + S5
@@ -231,14 +265,24 @@ __global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
   const double alpha = st->alpha;
   const int L = xcd_block(blockIdx.x, gridDim.x);
   const Range R = block_rows(A.n, L, gridDim.x);
-  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double q = fma(-alpha, V.s[i], V.r[i]);
-    V.q[i] = q;
-    V.qh[i] = A.dinv[i] * q;
+  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+    const int i1 = i0 + blockDim.x;
+    const bool two = i1 < R.hi;
+    const int j1 = two ? i1 : i0;
+    const double s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
+    const double d0 = A.dinv[i0], d1 = A.dinv[j1];
+    const double q0 = fma(-alpha, s0, r0);  // S4
+    V.q[i0] = q0;
+    V.qh[i0] = d0 * q0;                     // S5
+    if (two) {
+      const double q1 = fma(-alpha, s1, r1);
+      V.q[i1] = q1;
+      V.qh[i1] = d1 * q1;
+    }
   }
 }
 
-// D: S6 + S7
+// D: S6 + S7 partials
 template <int N>
 __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
@@ -253,19 +297,18 @@ __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
     const int i = base + threadIdx.x;
     const bool ok = i < R.hi;
+    const double q = ok ? V.q[i] : 0.0;
     const double yi = rows_wave<N>(A, V.qh, i, ok, s.wsa);
     if (ok) {
       V.y[i] = yi;
-      d[0].add(V.q[i], yi, s.sa, &s.flag[0]);
+      d[0].add(q, yi, s.sa, &s.flag[0]);
       d[1].add(yi, yi, s.sa + SA_D, &s.flag[1]);
     }
   }
-  if (!block_publish<N, 2>(d, s, red, 0, &red.tickets[3])) return;
-  block_finalize<N, 2>(s, red, 0);
-  if (threadIdx.x == 0) step_omega(V.st, hist_row(V, V.st->iter), s.res[0], s.res[1], 2);
+  block_publish<N, 2>(d, s, red, 0);
 }
 
-// E: S8 + S9 + S10/S11
+// E: S8 + S9 + S10/S11 partials
 template <int N>
 __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
   const State* st = V.st;
@@ -280,21 +323,38 @@ __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
-  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double x = fma(omega, V.qh[i], fma(alpha, V.ph[i], V.x[i]));
-    const double r = fma(-omega, V.y[i], V.q[i]);
-    V.x[i] = x;
-    V.r[i] = r;
-    record_xr(V, iter, A.n, i, x, r);
-    d[0].add(V.r0[i], r, s.sa, &s.flag[0]);
-    d[1].add(r, r, s.sa + SA_D, &s.flag[1]);
+  // two rows per step, every load issued before any store
+  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+    const int i1 = i0 + blockDim.x;
+    const bool two = i1 < R.hi;
+    double qh[2], ph[2], xo[2], y[2], q[2], r0[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = u ? (two ? i1 : i0) : i0;
+      qh[u] = V.qh[i];
+      ph[u] = V.ph[i];
+      xo[u] = V.x[i];
+      y[u] = V.y[i];
+      q[u] = V.q[i];
+      r0[u] = V.r0[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const int i = u ? i1 : i0;
+      const double x = fma(omega, qh[u], fma(alpha, ph[u], xo[u]));  // S8
+      const double r = fma(-omega, y[u], q[u]);                       // S9
+      V.x[i] = x;
+      V.r[i] = r;
+      record_xr(V, iter, A.n, i, x, r);
+      d[0].add(r0[u], r, s.sa, &s.flag[0]);                           // S10
+      d[1].add(r, r, s.sa + SA_D, &s.flag[1]);                        // S11
+    }
   }
-  if (!block_publish<N, 2>(d, s, red, 0, &red.tickets[4])) return;
-  block_finalize<N, 2>(s, red, 0);
-  if (threadIdx.x == 0) step_std_beta(V.st, hist_row(V, iter), s.res[0], s.res[1]);
+  block_publish<N, 2>(d, s, red, 0);
 }
 
-// true residual ||b - A x|| (reported at exit)
+// true residual ||b - A x|| (reported at exit): partial <e, e> (slot 0)
 template <int N>
 __global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
@@ -313,9 +373,38 @@ __global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
       d[0].add(e, e, s.sa, &s.flag[0]);
     }
   }
-  if (!block_publish<N, 1>(d, s, red, 0, &red.tickets[5])) return;
-  block_finalize<N, 1>(s, red, 0);
-  if (threadIdx.x == 0) V.st->true_res = sqrt(s.res[0]);
+  block_publish<N, 1>(d, s, red, 0);
+}
+
+// One workgroup: round the published dot products, take the scalar step.
+enum : int { FIN_ENTRY = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_BETA = 3, FIN_RESID = 4 };
+
+template <int N, int K, int F>
+__global__ void __launch_bounds__(1024) k_finish(Vecs V, Red red) {
+  State* st = V.st;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, K, false);
+  FinPre<N, K> pre;
+  fin_prefetch(pre, red, 0);  // record loads in flight before anything waits
+  State S;
+  state_load(S, st);
+  if (F != FIN_ENTRY && F != FIN_RESID && S.done) return;
+  shm_init(s, K);
+  block_finalize<N, K>(s, red, 0, &pre);
+  if (threadIdx.x != 0) return;
+  if constexpr (F == FIN_ENTRY) {
+    step_entry(&S, s.res[0]);
+    step_loop_entry(&S);
+  } else if constexpr (F == FIN_ALPHA) {
+    step_std_alpha(&S, hist_row(V, S.iter), s.res[0]);
+  } else if constexpr (F == FIN_OMEGA) {
+    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 2);
+  } else if constexpr (F == FIN_BETA) {
+    step_std_beta(&S, hist_row(V, S.iter), s.res[0], s.res[1]);
+  } else {
+    S.true_res = sqrt(s.res[0]);
+  }
+  state_store(st, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,7 +432,7 @@ __global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0, nullptr);
+  block_publish<N, 1>(d, s, red, 0);
 }
 
 // set-up 2: w = A r^, w^ = M^-1 w ; partial <r0, w> (slot 1)
@@ -366,7 +455,7 @@ __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
       d[0].add(V.r0[i], wi, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 1, nullptr);
+  block_publish<N, 1>(d, s, red, 1);
 }
 
 // SpMV kernels of the pipelined loop: workgroup with logical index 0 finishes
@@ -433,7 +522,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
   }
-  block_publish<N, 2>(d, s, red, 0, nullptr);
+  block_publish<N, 2>(d, s, red, 0);
 }
 
 // P2: S10 v = A z^ || S11 omega
@@ -480,7 +569,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
     d[3].add(r0, V.z[i], s.sa + 3 * SA_D, &s.flag[3]);
     d[4].add(r, r, s.sa + 4 * SA_D, &s.flag[4]);
   }
-  block_publish<N, 5>(d, s, red, 0, nullptr);
+  block_publish<N, 5>(d, s, red, 0);
 }
 
 // P4: S18 t = A w^ || S19

@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau0", ctypes.c_double),
                 ("tau", ctypes.c_double), ("true_res", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 8), ("phase_launches", ctypes.c_int32 * 8)]
+                ("phase_ms", ctypes.c_double * 12), ("phase_launches", ctypes.c_int32 * 12)]
 
 
 EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
