@@ -90,6 +90,24 @@ __device__ __forceinline__ double fpe_add_from(Fpe<N>& f, double x) {
   return x;
 }
 
+// Insert x from component S with a wave-uniform early exit: a level is skipped
+// only when no lane of the wavefront still carries a non-zero error; otherwise
+// every lane runs it (a twosum with x = 0 leaves the component's value
+// unchanged), which avoids per-lane control flow.  Same exact result as
+// fpe_add_from<N, S>; only the instruction count differs.
+template <int N, int S>
+__device__ __forceinline__ double fpe_add_w(Fpe<N>& f, double x) {
+#pragma unroll
+  for (int k = S; k < N; ++k) {
+    if (__ballot(x != 0.0) == 0ull) break;
+    double r, s;
+    two_sum(f.c[k], x, r, s);
+    f.c[k] = r;
+    x = s;
+  }
+  return x;
+}
+
 // Correct rounding (nearest, ties to even) of the exact sum of an FPE whose sum
 // is below 2^1022 in magnitude.
 //  1. Grow-expansion (Shewchuk 1997, Thm. 10): inserting the components one by
@@ -428,8 +446,8 @@ __device__ __forceinline__ void acc_prod(Fpe<N>& f, double a, double b, long lon
   const double ap = fabs(p);
   if (ap >= kProdLo && ap < kProdHi) {
     const double e = fma(a, b, -p);
-    const double l1 = fpe_add(f, p);
-    const double l2 = fpe_add_from<N, (N > 1 ? 1 : 0)>(f, e);
+    const double l1 = fpe_add_w<N, 0>(f, p);
+    const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
     if (l1 != 0.0 || l2 != 0.0) {
       sa_add_double(sa, l1);
       sa_add_double(sa, l2);

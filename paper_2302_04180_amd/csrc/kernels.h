@@ -64,21 +64,26 @@ struct Red {
 // ---------------------------------------------------------------------------
 // LDS layout
 // ---------------------------------------------------------------------------
+// lanes per scatter round: all 64 for workgroups of up to 512 threads, 32 for larger ones
+__host__ __device__ inline int scat_rows(int block) { return block <= 512 ? 64 : 32; }
+
 __host__ __device__ inline size_t shm_bytes(int N, int K, bool rows, int block) {
+  (void)rows;
   const size_t nw = (size_t)block / 64;
   const size_t sa = (N > 0) ? (size_t)K * SA_D * 8 : 0;
-  const size_t wsa = (rows && N > 0) ? nw * SA_D * 8 : 0;
-  const size_t scat = (N > 0) ? nw * 16 * WIN * 8 : 0;   // per wave: 16 lanes x WIN digits; >= block*8 bytes
+  // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D) and
+  // the finisher's per-wave accumulators use the same space at other times
+  const size_t scat = (N > 0) ? nw * scat_rows(block) * WIN * 8 : 0;
   const size_t wsum = (N > 0) ? 16 * WIN * 8 : 0;
-  return sa + wsa + scat + wsum + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
+  return sa + scat + wsum + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
 }
 
 template <int N>
 struct Shm {
   long long* sa;    // K * SA_D    long accumulators (rare path)
-  long long* wsa;   // nw * SA_D   row fallback accumulators
-  long long* scat;  // nw * 16 * WIN scatter rows; also the finisher's group sums
-  long long* wsum;  // 16 * WIN    per-wave window sums; also the finisher's window
+  long long* wsa;   // nw * SA_D   row fallback accumulators (aliases scat)
+  long long* scat;  // nw * rows * WIN scatter rows; also the finisher's per-wave accumulators
+  long long* wsum;  // 16 * WIN    per-wave window sums
   double* pbuf;     // 16          plain per-wave sums
   int* imax;        // 16 * MAX_DOTS per-wave maxima
   double* res;      // MAX_DOTS
@@ -88,15 +93,15 @@ struct Shm {
 
 template <int N>
 __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
+  (void)rows;
   Shm<N> s;
   const size_t nw = blockDim.x / 64;
   size_t off = 0;
   s.sa = (long long*)(base + off);
   off += (N > 0) ? (size_t)K * SA_D * 8 : 0;
-  s.wsa = (long long*)(base + off);
-  off += (rows && N > 0) ? nw * SA_D * 8 : 0;
   s.scat = (long long*)(base + off);
-  off += (N > 0) ? nw * 16 * WIN * 8 : 0;
+  s.wsa = s.scat;
+  off += (N > 0) ? nw * scat_rows(blockDim.x) * WIN * 8 : 0;
   s.wsum = (long long*)(base + off);
   off += (N > 0) ? 16 * WIN * 8 : 0;
   s.pbuf = (double*)(base + off);
@@ -199,8 +204,8 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
       const double ap = fabs(p);
       if (ap >= kProdLo && ap < kProdHi) {
         const double e = fma(a[u], b[u], -p);
-        const double l1 = fpe_add(f, p);
-        const double l2 = fpe_add_from<N, (N > 1 ? 1 : 0)>(f, e);
+        const double l1 = fpe_add_w<N, 0>(f, p);
+        const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
         ovf |= (l1 != 0.0) | (l2 != 0.0);
       } else if (!(p == 0.0 && (a[u] == 0.0 || b[u] == 0.0))) {
         ovf = true;
@@ -363,29 +368,29 @@ __device__ __forceinline__ void row_deposit(long long* row, int d0, double c, lo
 }
 
 // Sum the lanes' FPEs of one dot exactly into rec[0..REC) (global): rec[0] = grid
-// digit of window digit 0, rec[1+k] = raw integer sum of digit k.
+// digit of window digit 0, rec[1+k] = raw integer sum of digit k.  Each lane
+// adds its components into a private LDS row of WIN digits; lanes then sum the
+// rows column-wise (4 lanes per column) and the waves' columns are added.
 template <int N>
 __device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, long long* sa, int* flag,
                                              long long* rec) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int t = -1;
+  double mx = 0.0;
 #pragma unroll
-  for (int k = 0; k < N; ++k)
-    if (f.c[k] != 0.0) {
-      const int td = top_digit(f.c[k]);
-      t = (td > t) ? td : t;
-    }
-  const int D = block_max_int(t, s);
+  for (int k = 0; k < N; ++k) mx = fmax(mx, fabs(f.c[k]));
+  const int D = block_max_int(mx != 0.0 ? top_digit(mx) : -1, s);
   if (D < 0) {
     if (threadIdx.x == 0) rec[0] = REC_EMPTY;
     return;
   }
   const int d0 = D - (WIN - 1);
-  long long* R = s.scat + (size_t)w * 16 * WIN;
-  long long col = 0;
-  for (int q = 0; q < 4; ++q) {
-    if ((lane >> 4) == q) {
-      long long* row = R + (lane & 15) * WIN;
+  const int rows = scat_rows(blockDim.x), quarter = rows / 4;
+  long long* R = s.scat + (size_t)w * rows * WIN;
+  const int col = lane % WIN, part = lane / WIN;  // lanes < 4*WIN: column, row quarter
+  long long colsum = 0;
+  for (int q = 0; q < 64 / rows; ++q) {
+    if (lane / rows == q) {
+      long long* row = R + (lane % rows) * WIN;
 #pragma unroll
       for (int i = 0; i < WIN; ++i) row[i] = 0;
 #pragma unroll
@@ -393,12 +398,14 @@ __device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, l
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    if (lane < WIN)
-      for (int r = 0; r < 16; ++r) col += R[r * WIN + lane];
+    if (lane < 4 * WIN)
+      for (int r = part * quarter; r < (part + 1) * quarter; ++r) colsum += R[r * WIN + col];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
   }
-  if (lane < WIN) s.wsum[w * WIN + lane] = col;
+  colsum += __shfl(colsum, (lane + WIN) & 63, 64) + __shfl(colsum, (lane + 2 * WIN) & 63, 64) +
+            __shfl(colsum, (lane + 3 * WIN) & 63, 64);
+  if (lane < WIN) s.wsum[w * WIN + lane] = colsum;
   __syncthreads();
   if (threadIdx.x < WIN) {
     long long tot = 0;
