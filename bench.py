@@ -8,8 +8,10 @@ the same GPU, the per-kernel times of one instrumented solve (roofline of the
 dominant kernel), and the exact CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --profile   (fixed short workload for rocprofv3 counter passes)
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +25,24 @@ HBM_PEAK_GBS = 8000.0
 N_EDGE = 128
 TOL = 1e-10
 MAXIT = 5000
+
+
+# HBM traffic of the dominant kernel, from two rocprofv3 --pmc passes over
+# `python3 bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; median per launch),
+# each scaled by what the same counter reads for the plain copy kernel of that
+# workload (512 MiB read + 512 MiB written).  Valid only while the kernel
+# sources still have the digest they had when the counters were taken.
+TRAFFIC = None
+
+
+def kernel_digest():
+    d = os.path.join(ROOT, "paper_2302_04180_amd", "csrc")
+    h = hashlib.sha256()
+    for nm in sorted(os.listdir(d)):
+        if nm.endswith((".h", ".hip")):
+            with open(os.path.join(d, nm), "rb") as f:
+                h.update(nm.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -59,6 +79,32 @@ def cpu_baseline(A, n_iter):
                       "of the same 128^3 system; %.1f s" % (res["iters"], dt)}
 
 
+def profile_workload():
+    """Short fixed workload for counter passes: a plain copy kernel of known size
+    (scale reference for FETCH_SIZE / WRITE_SIZE), then 20 iterations of each
+    solver configuration with direct kernel launches."""
+    import torch
+
+    from paper_2302_04180_amd import inputs, rpk
+    torch.cuda.set_device(0)
+    src = torch.rand(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)  # reads 512 MiB, writes 512 MiB
+    torch.cuda.synchronize()
+    del src, dst
+    A = inputs.poisson7(N_EDGE)
+    n = N_EDGE ** 3
+    M = rpk.Matrix(*A)
+    b = rpk.exspmv(M, torch.ones(n, dtype=torch.float64, device="cuda"))
+    for variant in (rpk.STD, rpk.PIPELINED):
+        for dots in (rpk.EXACT, rpk.PLAIN):
+            rpk.solve(M, b, tol=TOL, maxit=20, variant=variant, dots=dots, graph=-1)
+    torch.cuda.synchronize()
+    M.close()
+    print("profile workload done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,11 +112,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--profile", action="store_true", help="run the fixed counter-collection workload only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        return profile_workload()
 
     import numpy as np
     import torch
@@ -134,8 +183,11 @@ def main():
     avg_s = tinfo["phase_ms"][dom] / tinfo["phase_launches"][dom] / 1e3
     dom_bytes = by["std_kernel"][dom]
     achieved = dom_bytes / avg_s / 1e9
+    traffic = None
+    if TRAFFIC and TRAFFIC["src_sha256"] == kernel_digest() and TRAFFIC["phase"] == dom:
+        traffic = TRAFFIC["bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[dom], "bytes_per_launch": dom_bytes, "avg_launch_us": round(avg_s * 1e6, 2)}
 
     result = {
