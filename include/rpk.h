@@ -49,7 +49,9 @@ typedef enum {
   RPK_ERR_ZERO_DIAG = 4,   /* a row has no diagonal, a repeated one, or a 0     */
   RPK_ERR_NONFINITE = 5,   /* NaN/Inf in the matrix, b, x0, or a dot product    */
   RPK_NOT_CONVERGED = 6,   /* maxit iterations without reaching tol             */
-  RPK_BREAKDOWN = 7        /* a zero denominator (<r0,s>, rho, omega or delta)  */
+  RPK_BREAKDOWN = 7,       /* a zero denominator (<r0,s>, rho, omega or delta)  */
+  RPK_PENDING = 8,         /* server: the request has not finished yet          */
+  RPK_REJECTED = 9         /* server: the request can never fit the HBM budget  */
 } rpk_status;
 
 typedef enum { RPK_STD = 0, RPK_PIPELINED = 1 } rpk_variant;
@@ -69,6 +71,8 @@ typedef struct {
                      long accumulator); 0 = 4 */
   int32_t graph;  /* solve: iterations per captured HIP graph launch; 0 = automatic,
                      -1 = no graph (direct launches) */
+  int32_t tile;   /* batched solve: rows per tile, a multiple of 64 in [64, 2^20];
+                     0 = chosen by the autotuner (together with block and fpe) */
 } rpk_launch;
 
 typedef struct {
@@ -92,6 +96,9 @@ typedef struct {
   double true_res;     /* ||b - A x|| of the returned x (exact dots/rows)     */
   double phase_ms[RPK_NPHASE];   /* timing mode: summed kernel times per phase */
   int32_t phase_launches[RPK_NPHASE];
+  rpk_launch used;     /* the launch shape that ran (after defaults / autotuning) */
+  double queue_ms;     /* server: submission -> admission (host monotonic clock) */
+  double latency_ms;   /* server: submission -> result ready                     */
 } rpk_info;
 
 typedef struct rpk_matrix rpk_matrix;
@@ -146,6 +153,85 @@ rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* opts, 
  * iterate.  Blocks until the solve is finished. */
 rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_opts* opts, void* ws,
                      size_t ws_bytes, void* stream, rpk_info* info);
+
+/* Workspace size of rpk_solve_batched for these nsys systems and options. */
+rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* opts,
+                                             size_t* bytes);
+
+/* Solve nsys independent systems A[k] x[k] = b[k] (host arrays of handles and of
+ * device pointers) together: every phase of the iteration is one launch over the
+ * rows of all systems still running, each system with its own scalars, stop
+ * test and status (Fig. 2 / Fig. 3 per system, as rpk_solve).  Each system's
+ * iterates, scalars, iteration count and x are bit-identical to rpk_solve of
+ * that system alone (the exact reductions make the grouping invisible).
+ * opts: as rpk_solve; hist, when set, holds nsys * maxit * RPK_HIST_W doubles
+ * (system k at offset k * maxit * RPK_HIST_W); xr_hist must be NULL; timing
+ * sums the batch's per-phase kernel times into infos[0].  launch.tile = 0 runs
+ * the autotuner on the first call for a batch shape (a few timed iterations of
+ * each candidate tile / workgroup / FPE configuration on scratch copies, caller
+ * data untouched) and caches its choice.  The x[k] must not overlap.  1 <= nsys
+ * <= 65536.  infos[k] receives system k's result and the launch used.  Returns
+ * RPK_OK when every system converged, else the status of the lowest-numbered
+ * system that did not.  Blocks until all systems have stopped. */
+rpk_status rpk_solve_batched(int32_t nsys, const rpk_matrix* const* A, const double* const* b, double* const* x,
+                             const rpk_opts* opts, void* ws, size_t ws_bytes, void* stream, rpk_info* infos);
+
+/* ---------------------------------------------------------------------------
+ * Request server (continuous batching).  A worker thread owns a HIP stream and
+ * advances every admitted solve together, one launch per phase for all of them
+ * (the batched kernels above), stopping every `chunk` iterations to retire
+ * finished solves and admit queued ones.  Admission is first come, first served
+ * by HBM footprint: a request is admitted when a slot is free and its workspace
+ * (solver vectors, reduction records, long accumulators) fits the free part of
+ * the server's budget; its Krylov state then stays in device memory until it
+ * finishes.  Each result is bit-identical to rpk_solve of the same system alone.
+ * ------------------------------------------------------------------------- */
+typedef struct rpk_server rpk_server;
+
+typedef struct {
+  size_t hbm_budget;   /* bytes of device memory for admitted solves (one
+                          allocation made at creation)                        */
+  int32_t max_slots;   /* solves in flight at most, 1 .. 65536                */
+  int32_t chunk;       /* iterations between admission points; 0 = 4          */
+  rpk_opts solve;      /* tol, maxit, variant, dots and launch.block / fpe /
+                          tile of every request; hist, xr_hist, timing: 0     */
+} rpk_server_opts;
+
+typedef struct {
+  int64_t submitted, admitted, completed, rejected;
+  int32_t queued, in_flight;
+  size_t bytes_in_use, bytes_peak;   /* of the HBM budget                    */
+  int64_t rounds;                    /* admission points passed              */
+  int64_t iterations;                /* batch iterations launched            */
+} rpk_server_stats;
+
+/* Create a server on the current device.  Errors: RPK_ERR_ARG (bad options),
+ * RPK_ERR_NOMEM (budget not allocatable), RPK_ERR_HIP. */
+rpk_status rpk_server_create(const rpk_server_opts* opts, rpk_server** out);
+
+/* Device bytes a request for matrix A occupies in the server's budget. */
+rpk_status rpk_server_footprint(const rpk_server* s, const rpk_matrix* A, size_t* bytes);
+
+/* Queue the solve of A x = b (x holds x0 on entry and the solution at the end;
+ * b and x are device pointers borrowed until the request has finished; A must
+ * outlive it).  *ticket identifies the request.  RPK_REJECTED: its footprint
+ * exceeds the whole budget (nothing queued). */
+rpk_status rpk_server_submit(rpk_server* s, const rpk_matrix* A, const double* b, double* x, uint64_t* ticket);
+
+/* RPK_PENDING while the request runs or waits; once finished, fills *info
+ * (status, iterations, norms, queue and total latency) and returns RPK_OK; the
+ * solve's own status is info->status.  A finished ticket can be read once:
+ * afterwards it is unknown (RPK_ERR_ARG). */
+rpk_status rpk_server_poll(rpk_server* s, uint64_t ticket, rpk_info* info);
+
+/* As rpk_server_poll, but blocks until the request has finished. */
+rpk_status rpk_server_wait(rpk_server* s, uint64_t ticket, rpk_info* info);
+
+/* Counters of the server so far. */
+rpk_status rpk_server_get_stats(const rpk_server* s, rpk_server_stats* out);
+
+/* Finish every submitted request, stop the worker, free the budget. */
+rpk_status rpk_server_destroy(rpk_server* s);
 
 /* Test hook: q[i] = a[i]/b[i] and s[i] = sqrt(a[i]) with the device operations the
  * solver's scalar steps use (to check them against IEEE-754 on the host). */

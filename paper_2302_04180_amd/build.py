@@ -28,7 +28,8 @@ def build(verbose=False, jobs=None):
     with tempfile.TemporaryDirectory(prefix="rpk_build_") as tmp:
         units = [(["-DRPK_N=%d" % n], os.path.join(CSRC, "kern_inst.hip"), os.path.join(tmp, "kern_%d.o" % n))
                  for n in FPE_LENGTHS]
-        units.append(([], os.path.join(CSRC, "rpk.hip"), os.path.join(tmp, "rpk.o")))
+        for host in ("rpk", "batch", "server"):
+            units.append(([], os.path.join(CSRC, host + ".hip"), os.path.join(tmp, host + ".o")))
         cmds = [["hipcc", *HIPCC_FLAGS, *extra, "-c", src, "-o", obj] for extra, src, obj in units]
         jobs = jobs or min(len(cmds), max(1, (os.cpu_count() or 2)))
         running = []

@@ -1,0 +1,234 @@
+// batch.h -- many independent systems advanced together, one launch per phase.
+//
+// Each system keeps its own matrix, vectors, device state and reduction slots
+// (a SysDesc).  The rows of all systems are cut into tiles of consecutive rows
+// of one system; a phase launch walks the tile table (workgroup b takes tiles
+// b, b + gridDim.x, ...) and runs the same phase bodies as the single-system
+// kernels on each tile, publishing the tile's record into its own system's
+// slots.  One finishing workgroup per system then rounds that system's dot
+// products and takes its scalar step.  Every system therefore computes exactly
+// what it computes alone: batching changes which workgroup handles which rows,
+// and the exact reductions make that invisible in the results.
+//
+// The tile table, the list of systems and their counts live in device memory
+// and are read at launch time, so a captured graph stays valid when the host
+// rewrites them between launches (continuous batching).
+#pragma once
+#include "solver.h"
+
+namespace rpk {
+
+struct SysDesc {
+  Csr A;
+  Vecs V;
+  Red red;  // red.G = number of tiles of this system
+};
+
+struct Tile {
+  int sys;  // index into the SysDesc array; < 0 for a padding tile
+  int lo, hi;
+  int rec;  // record index of this tile in its system's slots (0 .. red.G - 1)
+};
+
+struct Batch {
+  const SysDesc* sys;
+  const Tile* tiles;
+  const int* order;  // [count[1]] system indices visited by the finishing workgroups
+  const int* count;  // [0] number of tiles, [1] number of systems in `order`
+};
+
+// Run body(desc, rows, rec) on every tile of the table assigned to this
+// workgroup (logical index b out of G).  CHECK: skip systems that have stopped.
+template <int N, int K, bool CHECK, class Body>
+__device__ __forceinline__ void tile_loop(const Batch& B, const Shm<N>& s, int b, int G, Body body) {
+  const int nt = B.count[0];
+  for (int t = b; t < nt; t += G) {
+    const Tile T = B.tiles[t];
+    if (T.sys < 0) continue;
+    const SysDesc& D = B.sys[T.sys];
+    if (CHECK && D.V.st->done) continue;
+    if (K > 0) shm_init(s, K);
+    body(D, Range{T.lo, T.hi}, T.rec);
+    __syncthreads();
+  }
+}
+
+template <int N, int K, int F>
+__device__ __forceinline__ void fin_loop(const Batch& B, const Shm<N>& s, int b, int G) {
+  const int ns = B.count[1];
+  for (int k = b; k < ns; k += G) {
+    const SysDesc& D = B.sys[B.order[k]];
+    finish_body<N, K, F>(D.V, D.red, s);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------
+// fresh device state and cleared reduction scratch for every listed system
+template <int N>
+__global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, int variant) {
+  const int ns = B.count[1];
+  for (int k = blockIdx.x; k < ns; k += gridDim.x) {
+    const SysDesc& D = B.sys[B.order[k]];
+    for (int i = threadIdx.x; i < MAX_DOTS * SA_D; i += blockDim.x) D.red.gsa[i] = 0;
+    if (threadIdx.x < MAX_DOTS) D.red.gflags[threadIdx.x] = 0;
+    if (threadIdx.x < 8) D.red.tickets[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+      State* st = D.V.st;
+      st->alpha = 0.0; st->omega = 0.0; st->beta = 0.0; st->rho = 0.0;
+      st->tau = 0.0; st->tau0 = 0.0; st->tol = tol; st->true_res = 0.0;
+      st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
+      st->variant = variant; st->pad0 = 0; st->pad1 = 0; st->pad2 = 0;
+    }
+  }
+}
+
+// pipelined loop: the vectors of iteration -1 that S1..S4 read start at zero
+template <int N>
+__global__ void __launch_bounds__(1024) kb_zero_pipe(Batch B) {
+  const int nt = B.count[0];
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const Tile T = B.tiles[t];
+    if (T.sys < 0) continue;
+    const Vecs& V = B.sys[T.sys].V;
+    for (int i = T.lo + threadIdx.x; i < T.hi; i += blockDim.x) {
+      V.ph[i] = 0.0;
+      V.s[i] = 0.0;
+      V.sh[i] = 0.0;
+      V.z[i] = 0.0;
+      V.zh[i] = 0.0;
+      V.v[i] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// standard loop (kernels A, B, fin, C, D, fin, E, fin as for one system)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_init(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    std_init_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_A(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 0, false);
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
+                        [&](const SysDesc& D, Range R, int) { std_A_body(D.A, D.V, R); });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_B(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    std_B_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_C(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 0, false);
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
+                        [&](const SysDesc& D, Range R, int) { std_C_body(D.A, D.V, R); });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_D(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    std_D_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_std_E(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    std_E_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_resid(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    resid_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N, int K, int F>
+__global__ void __launch_bounds__(1024) kb_finish(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, K, false);
+  fin_loop<N, K, F>(B, s, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// pipelined loop
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pipe_init1(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_init1_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pipe_init2(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_init2_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_P1_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 5, false);
+  tile_loop<N, 5, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_P3_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+// SpMV of the pipelined loop over all tiles || the pending reduction of every
+// system: workgroups 0 .. Gf-1 finish systems, the others walk the tiles.
+// W selects the product: 0: t = A w^ (set-up 3, S18), 1: v = A z^ (S10).
+template <int N, int K, int F, int W, bool CHECK>
+__global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B, int Gf) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, K, true);
+  if ((int)blockIdx.x < Gf) {
+    fin_loop<N, K, F>(B, s, blockIdx.x, Gf);
+    return;
+  }
+  tile_loop<N, 0, CHECK>(B, s, blockIdx.x - Gf, gridDim.x - Gf, [&](const SysDesc& D, Range R, int) {
+    if (W == 0) spmv_body<N>(D.A, D.V.wh, D.V.t, R, s);
+    else spmv_body<N>(D.A, D.V.zh, D.V.v, R, s);
+  });
+}
+
+}  // namespace rpk

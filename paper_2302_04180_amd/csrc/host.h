@@ -1,0 +1,112 @@
+// host.h -- host-side pieces shared by the single-system solver (rpk.hip), the
+// batched solver (batch.hip) and the request server (server.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "kern.h"
+#include "rpk.h"
+
+struct rpk_matrix {
+  int64_t n = 0, nnz = 0;
+  int* rp = nullptr;  // CSR as given (validated), kept for reference
+  int* ci = nullptr;
+  double* v = nullptr;
+  double* dinv = nullptr;
+  int nslices = 0;    // SELL-64 copy used by the kernels
+  long long* sptr = nullptr;
+  int* scol = nullptr;
+  double* sval = nullptr;
+};
+
+namespace rpkhost {
+
+using namespace rpk;
+
+#define HIPCHK(call)                              \
+  do {                                            \
+    if ((call) != hipSuccess) return RPK_ERR_HIP; \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n}; }
+
+inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : 16; }
+
+template <template <int> class F, typename... Args>
+rpk_status by_fpe(int N, Args&&... args) {
+  switch (N) {
+    case 0: return F<0>::call(args...);
+    case 1: return F<1>::call(args...);
+    case 2: return F<2>::call(args...);
+    case 4: return F<4>::call(args...);
+    case 8: return F<8>::call(args...);
+  }
+  return RPK_ERR_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of systems (batch.hip; also used by the server)
+// ---------------------------------------------------------------------------
+struct Plan {
+  std::vector<Tile> tiles;  // XCD-interleaved: tile t runs on XCD t % 8
+  std::vector<int> G;       // tiles per listed system
+};
+
+// Tiles of at most T rows for the listed systems (sizes n); Tile.sys is ids[k]
+// (or k when ids is null) and Tile.rec the tile's index inside its system.
+Plan make_plan(const std::vector<int64_t>& n, int T, const std::vector<int>* ids = nullptr);
+// upper bound of make_plan(n, T).tiles.size() for every T >= Tcap
+int64_t tile_capacity(const std::vector<int64_t>& n, int Tcap);
+
+// Device block of one system: tickets + flags | long accumulators | window
+// records for gcap tiles | nvec solver vectors of n doubles.
+constexpr size_t kFlagsBytes = 8 * sizeof(unsigned) + MAX_DOTS * sizeof(int);
+size_t sys_bytes(int64_t n, int gcap, int nvec);
+// Descriptor of a system whose block starts at `base` (device address).
+SysDesc make_desc(const rpk_matrix* A, const double* b, double* x, char* base, int gcap, int G, int variant,
+                  State* st, double* hist);
+
+// Library-wide state, guarded by g_mu: the capture stream, pinned state
+// buffers, and the cache of instantiated iteration graphs.  A graph key lists
+// every kernel argument the graph bakes in; key[0] is the matrix handle the
+// graph refers to (0 when its kernels find their systems through device memory).
+std::mutex& lib_mutex();
+hipStream_t capture_stream();
+rpk_status ensure_globals();
+// pinned host buffer of at least `count` States (valid until the next call)
+State* pinned_states(size_t count);
+hipGraphExec_t graph_find(const std::vector<uint64_t>& key);
+void graph_put(const std::vector<uint64_t>& key, hipGraphExec_t g);
+void graph_drop_owner(uint64_t owner);
+
+// Capture `body(capture_stream)` into a graph and instantiate it (cached by key).
+template <class Body>
+rpk_status graph_get(const std::vector<uint64_t>& key, Body body, hipGraphExec_t* out) {
+  hipGraphExec_t exec = graph_find(key);
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    hipStream_t cs = capture_stream();
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const rpk_status cst = body(cs);
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (cst != RPK_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return RPK_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return RPK_ERR_HIP;
+    graph_put(key, exec);
+  }
+  *out = exec;
+  return RPK_OK;
+}
+
+}  // namespace rpkhost

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rpk.h"
-#include "solver.h"
+#include "batch.h"
 
 namespace rpk {
 
@@ -25,10 +25,25 @@ struct Kern {
   static rpk_status phase(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red red);
 };
 
+// Batched launchers: G = workgroups of the tile-walking kernels, Gf = workgroups
+// of the finishing kernels (and of the finishing part of the pipelined SpMVs).
+template <int N>
+struct KernB {
+  static rpk_status setup(int Gf, hipStream_t s, Batch b, double tol, int maxit, int variant);
+  static rpk_status init(int variant, int G, int Gf, int B, hipStream_t s, Batch b);
+  static rpk_status resid(int G, int Gf, int B, hipStream_t s, Batch b);
+  static rpk_status phase(int variant, int ph, int G, int Gf, int B, hipStream_t s, Batch b);
+};
+
 extern template struct Kern<0>;
 extern template struct Kern<1>;
 extern template struct Kern<2>;
 extern template struct Kern<4>;
 extern template struct Kern<8>;
+extern template struct KernB<0>;
+extern template struct KernB<1>;
+extern template struct KernB<2>;
+extern template struct KernB<4>;
+extern template struct KernB<8>;
 
 }  // namespace rpk

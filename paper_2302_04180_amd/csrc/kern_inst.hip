@@ -63,6 +63,53 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
   }
 }
 
+template <int N>
+rpk_status KernB<N>::setup(int Gf, hipStream_t s, Batch b, double tol, int maxit, int variant) {
+  RET_IF(launch(kb_setup<N>, Gf, 256, 0, s, b, tol, maxit, variant));
+  if (variant == RPK_PIPELINED) return launch(kb_zero_pipe<N>, Gf, 1024, 0, s, b);
+  return RPK_OK;
+}
+
+template <int N>
+rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batch b) {
+  if (variant == RPK_STD) {
+    RET_IF(launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b));
+    return launch(kb_finish<N, 1, FIN_ENTRY>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
+  }
+  RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
+  RET_IF(launch(kb_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, b));
+  return launch(kb_pipe_spmv<N, 2, FIN_PENTRY, 0, false>, Gf + G, B, shm_bytes(N, 2, true, B), s, b, Gf);
+}
+
+template <int N>
+rpk_status KernB<N>::resid(int G, int Gf, int B, hipStream_t s, Batch b) {
+  RET_IF(launch(kb_resid<N>, G, B, shm_bytes(N, 1, true, B), s, b));
+  return launch(kb_finish<N, 1, FIN_RESID>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
+}
+
+template <int N>
+rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_t s, Batch b) {
+  if (variant == RPK_STD) {
+    switch (ph) {
+      case 0: return launch(kb_std_A<N>, G, B, 0, s, b);
+      case 1: return launch(kb_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, b);
+      case 2: return launch(kb_finish<N, 1, FIN_ALPHA>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
+      case 3: return launch(kb_std_C<N>, G, B, 0, s, b);
+      case 4: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
+      case 5: return launch(kb_finish<N, 2, FIN_OMEGA>, Gf, FB, shm_bytes(N, 2, false, FB), s, b);
+      case 6: return launch(kb_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+      default: return launch(kb_finish<N, 2, FIN_BETA>, Gf, FB, shm_bytes(N, 2, false, FB), s, b);
+    }
+  }
+  switch (ph) {
+    case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+    case 1: return launch(kb_pipe_spmv<N, 2, FIN_POMEGA, 1, true>, Gf + G, B, shm_bytes(N, 2, true, B), s, b, Gf);
+    case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, b);
+    default: return launch(kb_pipe_spmv<N, 5, FIN_S19, 0, true>, Gf + G, B, shm_bytes(N, 5, true, B), s, b, Gf);
+  }
+}
+
 template struct Kern<RPK_N>;
+template struct KernB<RPK_N>;
 
 }  // namespace rpk

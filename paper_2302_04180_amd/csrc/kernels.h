@@ -418,9 +418,9 @@ __device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, l
 
 // Publish the K dots of this workgroup (records or plain partials) to slots
 // slot0..slot0+K-1; rare long-accumulator content goes to the global ones.
+// `b` is the record index of this workgroup (0 <= b < red.G).
 template <int N, int K>
-__device__ __forceinline__ void block_publish(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0) {
-  const int b = blockIdx.x;  // publishing kernels run exactly red.G workgroups
+__device__ __forceinline__ void block_publish(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0, int b) {
   if constexpr (N > 0) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(1024) k_dot(long long n, const double* __restr
   Dot<N> d[1];
   d[0].zero();
   for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) d[0].add(x[i], y[i], s.sa, &s.flag[0]);
-  block_publish<N, 1>(d, s, red, 0);
+  block_publish<N, 1>(d, s, red, 0, blockIdx.x);
 }
 
 template <int N>

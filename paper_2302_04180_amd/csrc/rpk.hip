@@ -14,30 +14,13 @@
 #include <tuple>
 #include <vector>
 
-#include "rpk.h"
-#include "kern.h"
+#include "host.h"
 #include "setup.h"
 
 using namespace rpk;
-
-struct rpk_matrix {
-  int64_t n = 0, nnz = 0;
-  int* rp = nullptr;  // CSR as given (validated), kept for reference
-  int* ci = nullptr;
-  double* v = nullptr;
-  double* dinv = nullptr;
-  int nslices = 0;    // SELL-64 copy used by the kernels
-  long long* sptr = nullptr;
-  int* scol = nullptr;
-  double* sval = nullptr;
-};
+using namespace rpkhost;
 
 namespace {
-
-#define HIPCHK(call)                            \
-  do {                                          \
-    if ((call) != hipSuccess) return RPK_ERR_HIP; \
-  } while (0)
 
 struct Cfg {
   int block, grid, fpe, graph;
@@ -64,9 +47,6 @@ rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
   }
   return RPK_OK;
 }
-
-constexpr size_t kAlign = 256;
-size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // workspace header: state | tickets+flags | long accumulators | partials
 struct Layout {
@@ -101,22 +81,6 @@ Red make_red(char* ws, const Layout& l, int grid) {
   return r;
 }
 
-int nvec_of(int variant) { return variant == RPK_STD ? 8 : 16; }
-
-Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n}; }
-
-template <template <int> class F, typename... Args>
-rpk_status by_fpe(int N, Args&&... args) {
-  switch (N) {
-    case 0: return F<0>::call(args...);
-    case 1: return F<1>::call(args...);
-    case 2: return F<2>::call(args...);
-    case 4: return F<4>::call(args...);
-    case 8: return F<8>::call(args...);
-  }
-  return RPK_ERR_ARG;
-}
-
 template <int N>
 struct DotF {
   static rpk_status call(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* o,
@@ -144,25 +108,58 @@ struct PhaseF {
 };
 
 // ---------------------------------------------------------------------------
-// graph cache: one executable graph per (matrix, buffers, shape, chunk)
+// library-wide state
 // ---------------------------------------------------------------------------
-using GraphKey = std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, int, int, int,
-                            int, int>;
 std::mutex g_mu;
-std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
 hipStream_t g_capture = nullptr;
 State* g_pinned = nullptr;
+size_t g_pinned_count = 0;
+
+}  // namespace
+
+namespace rpkhost {
+
+std::mutex& lib_mutex() { return g_mu; }
+hipStream_t capture_stream() { return g_capture; }
 
 rpk_status ensure_globals() {
   if (!g_capture) HIPCHK(hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking));
-  if (!g_pinned) HIPCHK(hipHostMalloc((void**)&g_pinned, sizeof(State), hipHostMallocDefault));
+  if (!g_pinned) {
+    HIPCHK(hipHostMalloc((void**)&g_pinned, sizeof(State), hipHostMallocDefault));
+    g_pinned_count = 1;
+  }
   return RPK_OK;
 }
 
-void drop_graphs(const rpk_matrix* A) {
+State* pinned_states(size_t count) {
+  if (count > g_pinned_count) {
+    State* p = nullptr;
+    if (hipHostMalloc((void**)&p, count * sizeof(State), hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (g_pinned) (void)hipHostFree(g_pinned);
+    g_pinned = p;
+    g_pinned_count = count;
+  }
+  return g_pinned;
+}
+
+hipGraphExec_t graph_find(const std::vector<uint64_t>& key) {
+  auto it = g_graphs.find(key);
+  return it == g_graphs.end() ? nullptr : it->second;
+}
+
+void graph_put(const std::vector<uint64_t>& key, hipGraphExec_t g) {
+  if (g_graphs.size() >= 256) {  // bound the cache: drop everything (rebuilt on demand)
+    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+  }
+  g_graphs[key] = g;
+}
+
+void graph_drop_owner(uint64_t owner) {
   for (auto it = g_graphs.begin(); it != g_graphs.end();) {
-    if (std::get<0>(it->first) == (const void*)A) {
-      hipGraphExecDestroy(it->second);
+    if (!it->first.empty() && it->first[0] == owner) {
+      (void)hipGraphExecDestroy(it->second);
       it = g_graphs.erase(it);
     } else {
       ++it;
@@ -170,7 +167,7 @@ void drop_graphs(const rpk_matrix* A) {
   }
 }
 
-}  // namespace
+}  // namespace rpkhost
 
 // ===========================================================================
 // C ABI
@@ -299,7 +296,7 @@ rpk_status rpk_matrix_destroy(rpk_matrix* A) {
   if (!A) return RPK_ERR_ARG;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    drop_graphs(A);
+    graph_drop_owner((uint64_t)(uintptr_t)A);
   }
   free_matrix(A);
   return RPK_OK;
@@ -388,6 +385,10 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   RET_IF(resolve(&o->launch, A->n, &c));
   const Layout l = layout(c.grid, A->n, nvec_of(o->variant));
   if (ws_bytes < l.total) return RPK_ERR_ARG;
+  info->used.block = c.block;
+  info->used.grid = c.grid;
+  info->used.fpe = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  info->used.graph = c.graph;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
   RET_IF(ensure_globals());
@@ -469,25 +470,19 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
         }
         launched += 1;
       } else if (use_graph) {
-        GraphKey key{A, b, x, ws, o->hist, o->xr_hist, variant, N, G, B, chunk};
-        auto it = g_graphs.find(key);
+        const std::vector<uint64_t> key{(uint64_t)(uintptr_t)A, (uint64_t)(uintptr_t)b, (uint64_t)(uintptr_t)x,
+                                        (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)o->hist,
+                                        (uint64_t)(uintptr_t)o->xr_hist, (uint64_t)variant, (uint64_t)N,
+                                        (uint64_t)G, (uint64_t)B, (uint64_t)chunk};
         hipGraphExec_t exec = nullptr;
-        if (it == g_graphs.end()) {
-          hipGraph_t graph = nullptr;
-          if (hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal) != hipSuccess) { st = RPK_ERR_HIP; break; }
+        st = graph_get(key, [&](hipStream_t cs) {
           rpk_status cst = RPK_OK;
           for (int k = 0; k < chunk && cst == RPK_OK; ++k)
             for (int ph = 0; ph < nph && cst == RPK_OK; ++ph)
-              cst = by_fpe<PhaseF>(N, variant, ph, G, B, g_capture, Ac, V, red);
-          const hipError_t ec = hipStreamEndCapture(g_capture, &graph);
-          if (cst != RPK_OK || ec != hipSuccess) { st = RPK_ERR_HIP; if (graph) hipGraphDestroy(graph); break; }
-          const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-          hipGraphDestroy(graph);
-          if (ei != hipSuccess) { st = RPK_ERR_HIP; break; }
-          g_graphs[key] = exec;
-        } else {
-          exec = it->second;
-        }
+              cst = by_fpe<PhaseF>(N, variant, ph, G, B, cs, Ac, V, red);
+          return cst;
+        }, &exec);
+        if (st != RPK_OK) break;
         if (hipGraphLaunch(exec, s) != hipSuccess) { st = RPK_ERR_HIP; break; }
         launched += chunk;
       } else {

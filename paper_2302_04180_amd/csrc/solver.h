@@ -168,16 +168,15 @@ __device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double
 }
 
 // ---------------------------------------------------------------------------
-// standard loop
+// Phase bodies.  Each works on the rows [R.lo, R.hi) of one system (R.lo a
+// multiple of 64) and publishes its dot partials as record `rec` of that
+// system's reduction slots; the single-system kernels below and the batched
+// kernels (one tile of one system per workgroup) both run them.
 // ---------------------------------------------------------------------------
 // r0 := b - A x0, p := r0 ; partial <r0, r0> (slot 0)
 template <int N>
-__global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, true);
-  shm_init(s, 1);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void std_init_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                              const Shm<N>& s) {
   Dot<N> d[1];
   d[0].zero();
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
@@ -192,18 +191,14 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0);
+  block_publish<N, 1>(d, s, red, 0, rec);
 }
 
 // A: S12 (iterations after the first) and S1
-template <int N>
-__global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
+__device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R) {
   const State* st = V.st;
-  if (st->done) return;
   const bool upd = st->iter > 0;
   const double beta = st->beta, omega = st->omega;
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
     const bool two = i1 < R.hi;
@@ -235,13 +230,8 @@ __global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
 
 // B: S2 + S3 partial
 template <int N>
-__global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, true);
-  shm_init(s, 1);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                           const Shm<N>& s) {
   Dot<N> d[1];
   d[0].zero();
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
@@ -254,17 +244,12 @@ __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
       d[0].add(r0, si, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0);
+  block_publish<N, 1>(d, s, red, 0, rec);
 }
 
 // C: S4 + S5
-template <int N>
-__global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
-  const State* st = V.st;
-  if (st->done) return;
-  const double alpha = st->alpha;
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R) {
+  const double alpha = V.st->alpha;
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
     const bool two = i1 < R.hi;
@@ -284,13 +269,8 @@ __global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
 
 // D: S6 + S7 partials
 template <int N>
-__global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, true);
-  shm_init(s, 2);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                           const Shm<N>& s) {
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
@@ -305,21 +285,16 @@ __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
       d[1].add(yi, yi, s.sa + SA_D, &s.flag[1]);
     }
   }
-  block_publish<N, 2>(d, s, red, 0);
+  block_publish<N, 2>(d, s, red, 0, rec);
 }
 
 // E: S8 + S9 + S10/S11 partials
 template <int N>
-__global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
+__device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                           const Shm<N>& s) {
   const State* st = V.st;
-  if (st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, false);
-  shm_init(s, 2);
   const double alpha = st->alpha, omega = st->omega;
   const int iter = st->iter;
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
@@ -351,17 +326,13 @@ __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
       d[1].add(r, r, s.sa + SA_D, &s.flag[1]);                        // S11
     }
   }
-  block_publish<N, 2>(d, s, red, 0);
+  block_publish<N, 2>(d, s, red, 0, rec);
 }
 
 // true residual ||b - A x|| (reported at exit): partial <e, e> (slot 0)
 template <int N>
-__global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, true);
-  shm_init(s, 1);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void resid_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                           const Shm<N>& s) {
   Dot<N> d[1];
   d[0].zero();
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
@@ -373,51 +344,13 @@ __global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
       d[0].add(e, e, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0);
+  block_publish<N, 1>(d, s, red, 0, rec);
 }
 
-// One workgroup: round the published dot products, take the scalar step.
-enum : int { FIN_ENTRY = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_BETA = 3, FIN_RESID = 4 };
-
-template <int N, int K, int F>
-__global__ void __launch_bounds__(1024) k_finish(Vecs V, Red red) {
-  State* st = V.st;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, K, false);
-  FinPre<N, K> pre;
-  fin_prefetch(pre, red, 0);  // record loads in flight before anything waits
-  State S;
-  state_load(S, st);
-  if (F != FIN_ENTRY && F != FIN_RESID && S.done) return;
-  shm_init(s, K);
-  block_finalize<N, K>(s, red, 0, &pre);
-  if (threadIdx.x != 0) return;
-  if constexpr (F == FIN_ENTRY) {
-    step_entry(&S, s.res[0]);
-    step_loop_entry(&S);
-  } else if constexpr (F == FIN_ALPHA) {
-    step_std_alpha(&S, hist_row(V, S.iter), s.res[0]);
-  } else if constexpr (F == FIN_OMEGA) {
-    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 2);
-  } else if constexpr (F == FIN_BETA) {
-    step_std_beta(&S, hist_row(V, S.iter), s.res[0], s.res[1]);
-  } else {
-    S.true_res = sqrt(s.res[0]);
-  }
-  state_store(st, S);
-}
-
-// ---------------------------------------------------------------------------
-// pipelined loop
-// ---------------------------------------------------------------------------
-// set-up 1: r = b - A x0, r0 = r, r^ = M^-1 r ; partial <r0, r> (slot 0)
+// set-up 1 of the pipelined loop: r = b - A x0, r0 = r, r^ = M^-1 r ; partial <r0, r> (slot 0)
 template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, true);
-  shm_init(s, 1);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void pipe_init1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                                const Shm<N>& s) {
   Dot<N> d[1];
   d[0].zero();
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
@@ -432,17 +365,13 @@ __global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0);
+  block_publish<N, 1>(d, s, red, 0, rec);
 }
 
 // set-up 2: w = A r^, w^ = M^-1 w ; partial <r0, w> (slot 1)
 template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, true);
-  shm_init(s, 1);
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
+__device__ __forceinline__ void pipe_init2_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                                const Shm<N>& s) {
   Dot<N> d[1];
   d[0].zero();
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
@@ -455,50 +384,26 @@ __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
       d[0].add(V.r0[i], wi, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 1);
+  block_publish<N, 1>(d, s, red, 1, rec);
 }
 
-// SpMV kernels of the pipelined loop: workgroup with logical index 0 finishes
-// the pending reduction, the others compute out = A in.
-template <int N, int K>
-__device__ __forceinline__ int spmv_or_finish(const Csr& A, const double* in, double* out, const Shm<N>& s,
-                                              const Red& red) {
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  if (L == 0) {
-    block_finalize<N, K>(s, red, 0);
-    return 1;
-  }
-  const Range R = block_rows(A.n, L - 1, gridDim.x - 1);
+// out = A in on rows R (the SpMVs of the pipelined loop)
+template <int N>
+__device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double* out, Range R, const Shm<N>& s) {
   for (int base = R.lo; base < R.hi; base += blockDim.x) {
     const int i = base + threadIdx.x;
     const bool ok = i < R.hi;
     const double v = rows_wave<N>(A, in, i, ok, s.wsa);
     if (ok) out[i] = v;
   }
-  return 0;
-}
-
-// set-up 3: t = A w^ || alpha0 = <r0,r0> / <r0,w>
-template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_init3(Csr A, Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, true);
-  shm_init(s, 2);
-  if (spmv_or_finish<N, 2>(A, V.wh, V.t, s, red) && threadIdx.x == 0)
-    step_pipe_entry(V.st, s.res[0], s.res[1]);
 }
 
 // P1: S1..S7, S9 and the partials of S8 (slots 0, 1)
 template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
+__device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                             const Shm<N>& s) {
   const State* st = V.st;
-  if (st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, false);
-  shm_init(s, 2);
   const double alpha = st->alpha, beta = st->beta, omega = st->omega;
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
@@ -522,32 +427,16 @@ __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
   }
-  block_publish<N, 2>(d, s, red, 0);
-}
-
-// P2: S10 v = A z^ || S11 omega
-template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_P2(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, true);
-  shm_init(s, 2);
-  if (spmv_or_finish<N, 2>(A, V.zh, V.v, s, red) && threadIdx.x == 0)
-    step_omega(V.st, hist_row(V, V.st->iter), s.res[0], s.res[1], 0);
+  block_publish<N, 2>(d, s, red, 0, rec);
 }
 
 // P3: S12..S15, S17 and the partials of S16 + <r,r> (slots 0..4)
 template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
+__device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                             const Shm<N>& s) {
   const State* st = V.st;
-  if (st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 5, false);
-  shm_init(s, 5);
   const double alpha = st->alpha, omega = st->omega;
   const int iter = st->iter;
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  const Range R = block_rows(A.n, L, gridDim.x);
   Dot<N> d[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) d[j].zero();
@@ -569,7 +458,186 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
     d[3].add(r0, V.z[i], s.sa + 3 * SA_D, &s.flag[3]);
     d[4].add(r, r, s.sa + 4 * SA_D, &s.flag[4]);
   }
-  block_publish<N, 5>(d, s, red, 0);
+  block_publish<N, 5>(d, s, red, 0, rec);
+}
+
+// One finishing workgroup: round the K published dot products of one system
+// and take its scalar step.
+enum : int {
+  FIN_ENTRY = 0,     // <r0,r0>            -> tau0, loop entry test (standard)
+  FIN_ALPHA = 1,     // <r0,s>             -> alpha (S3)
+  FIN_OMEGA = 2,     // <q,y>, <y,y>       -> omega (S7)
+  FIN_BETA = 3,      // <r0,r>, <r,r>      -> tau, stop test, beta (S10, S11)
+  FIN_RESID = 4,     // <e,e>              -> true residual
+  FIN_PENTRY = 5,    // <r0,r0>, <r0,w>    -> tau0, alpha0 (pipelined set-up)
+  FIN_POMEGA = 6,    // <q,y>, <y,y>       -> omega (S11 of the pipelined loop)
+  FIN_S19 = 7        // 5 dots             -> S19
+};
+
+template <int N, int K, int F>
+__device__ __forceinline__ void finish_body(const Vecs& V, const Red& red, const Shm<N>& s) {
+  State* st = V.st;
+  FinPre<N, K> pre;
+  fin_prefetch(pre, red, 0);  // record loads in flight before anything waits
+  State S;
+  state_load(S, st);
+  if (F != FIN_ENTRY && F != FIN_RESID && F != FIN_PENTRY && S.done) return;
+  shm_init(s, K);
+  block_finalize<N, K>(s, red, 0, &pre);
+  if (threadIdx.x != 0) return;
+  if constexpr (F == FIN_ENTRY) {
+    step_entry(&S, s.res[0]);
+    step_loop_entry(&S);
+  } else if constexpr (F == FIN_ALPHA) {
+    step_std_alpha(&S, hist_row(V, S.iter), s.res[0]);
+  } else if constexpr (F == FIN_OMEGA) {
+    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 2);
+  } else if constexpr (F == FIN_BETA) {
+    step_std_beta(&S, hist_row(V, S.iter), s.res[0], s.res[1]);
+  } else if constexpr (F == FIN_RESID) {
+    S.true_res = sqrt(s.res[0]);
+  } else if constexpr (F == FIN_PENTRY) {
+    step_pipe_entry(&S, s.res[0], s.res[1]);
+  } else if constexpr (F == FIN_POMEGA) {
+    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 0);
+  } else {
+    step_pipe_s19(&S, hist_row(V, S.iter), s.res);
+  }
+  state_store(st, S);
+}
+
+// ---------------------------------------------------------------------------
+// Single-system kernels: logical workgroup L (XCD-aware) owns the L-th
+// contiguous row range and publishes record blockIdx.x.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Range my_rows(int n) {
+  return block_rows(n, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  std_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
+  if (V.st->done) return;
+  std_A_body(A, V, my_rows(A.n));
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  std_B_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
+  if (V.st->done) return;
+  std_C_body(A, V, my_rows(A.n));
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  shm_init(s, 2);
+  std_D_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  shm_init(s, 2);
+  std_E_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  resid_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N, int K, int F>
+__global__ void __launch_bounds__(1024) k_finish(Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, K, false);
+  finish_body<N, K, F>(V, red, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  pipe_init1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  pipe_init2_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+// SpMV kernels of the pipelined loop: the workgroup with logical index 0
+// finishes the pending reduction (F), the others compute out = A in.
+template <int N, int K, int F>
+__device__ __forceinline__ void spmv_or_finish(const Csr& A, const Vecs& V, const double* in, double* out,
+                                               const Shm<N>& s, const Red& red) {
+  const int L = xcd_block(blockIdx.x, gridDim.x);
+  if (L == 0) {
+    finish_body<N, K, F>(V, red, s);
+    return;
+  }
+  spmv_body<N>(A, in, out, block_rows(A.n, L - 1, gridDim.x - 1), s);
+}
+
+// set-up 3: t = A w^ || alpha0 = <r0,r0> / <r0,w>
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_init3(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  spmv_or_finish<N, 2, FIN_PENTRY>(A, V, V.wh, V.t, s, red);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  shm_init(s, 2);
+  pipe_P1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+// P2: S10 v = A z^ || S11 omega
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P2(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  spmv_or_finish<N, 2, FIN_POMEGA>(A, V, V.zh, V.v, s, red);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 5, false);
+  shm_init(s, 5);
+  pipe_P3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 // P4: S18 t = A w^ || S19
@@ -578,9 +646,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P4(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 5, true);
-  shm_init(s, 5);
-  if (spmv_or_finish<N, 5>(A, V.wh, V.t, s, red) && threadIdx.x == 0)
-    step_pipe_s19(V.st, hist_row(V, V.st->iter), s.res);
+  spmv_or_finish<N, 5, FIN_S19>(A, V, V.wh, V.t, s, red);
 }
 
 }  // namespace rpk

@@ -17,12 +17,12 @@ STD, PIPELINED = 0, 1
 EXACT, PLAIN = 0, 1
 HIST_W = 12
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_ZERO_DIAG",
-          5: "ERR_NONFINITE", 6: "NOT_CONVERGED", 7: "BREAKDOWN"}
+          5: "ERR_NONFINITE", 6: "NOT_CONVERGED", 7: "BREAKDOWN", 8: "PENDING", 9: "REJECTED"}
 
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("fpe", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -34,12 +34,28 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau0", ctypes.c_double),
                 ("tau", ctypes.c_double), ("true_res", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 12), ("phase_launches", ctypes.c_int32 * 12)]
+                ("phase_ms", ctypes.c_double * 12), ("phase_launches", ctypes.c_int32 * 12),
+                ("used", Launch), ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("solve", Opts)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("queued", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t), ("rounds", ctypes.c_int64),
+                ("iterations", ctypes.c_int64)]
 
 
 EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
            "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot",
-           "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_device_divsqrt"]
+           "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_solve_batched_workspace_bytes",
+           "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
+           "rpk_server_poll", "rpk_server_wait", "rpk_server_get_stats", "rpk_server_destroy",
+           "rpk_device_divsqrt"]
 
 _lib = None
 
@@ -66,6 +82,15 @@ def load(path=LIB_PATH):
     lib.rpk_exspmv.argtypes = [P, P, P, I32, ctypes.POINTER(Launch), P]
     lib.rpk_solve_workspace_bytes.argtypes = [P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
     lib.rpk_solve.argtypes = [P, P, P, ctypes.POINTER(Opts), P, S, P, ctypes.POINTER(Info)]
+    lib.rpk_solve_batched_workspace_bytes.argtypes = [I32, P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
+    lib.rpk_solve_batched.argtypes = [I32, P, P, P, ctypes.POINTER(Opts), P, S, P, P]
+    lib.rpk_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
+    lib.rpk_server_footprint.argtypes = [P, P, ctypes.POINTER(S)]
+    lib.rpk_server_submit.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rpk_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Info)]
+    lib.rpk_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Info)]
+    lib.rpk_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.rpk_server_destroy.argtypes = [P]
     lib.rpk_device_divsqrt.argtypes = [I64, P, P, P, P, P]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = I32
@@ -92,8 +117,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _launch(block=0, grid=0, fpe=0, graph=0):
-    return Launch(int(block), int(grid), int(fpe), int(graph))
+def _launch(block=0, grid=0, fpe=0, graph=0, tile=0):
+    return Launch(int(block), int(grid), int(fpe), int(graph), int(tile))
 
 
 def _dev(t):
@@ -208,14 +233,124 @@ def solve(A, b, x0=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, 
                          ctypes.byref(info))
     if code in (1, 2, 3):
         _check(code, "rpk_solve")
-    res = {"status": STATUS.get(info.status, info.status), "code": info.status, "iters": info.iters,
-           "tau0": info.tau0, "tau": info.tau, "true_res": info.true_res,
-           "phase_ms": list(info.phase_ms), "phase_launches": list(info.phase_launches)}
+    res = _info_dict(info)
     if record:
         res["hist"] = hist
     if record_xr:
         res["xr"] = xr
     return x, res
+
+
+def _info_dict(info):
+    u = info.used
+    return {"status": STATUS.get(info.status, info.status), "code": info.status, "iters": info.iters,
+            "tau0": info.tau0, "tau": info.tau, "true_res": info.true_res,
+            "phase_ms": list(info.phase_ms), "phase_launches": list(info.phase_launches),
+            "used": {"block": u.block, "grid": u.grid, "fpe": u.fpe, "graph": u.graph, "tile": u.tile},
+            "queue_ms": info.queue_ms, "latency_ms": info.latency_ms}
+
+
+def solve_batched(As, bs, x0s=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, grid=0, fpe=0,
+                  graph=0, tile=0, record=False, timing=False):
+    """Solve the independent systems As[k] x = bs[k] together (one launch per phase
+    for all of them).  Returns (xs, infos); with record=True infos[k]['hist'] is
+    system k's (maxit, HIST_W) history."""
+    lib = load()
+    ns = len(As)
+    assert ns == len(bs) and ns >= 1
+    bs = [_dev(b) for b in bs]
+    if x0s is None:
+        xs = [torch.zeros(A.n, dtype=torch.float64, device=b.device) for A, b in zip(As, bs)]
+    else:
+        xs = [_dev(x).clone() for x in x0s]
+    m = max(int(maxit), 1)
+    hist = torch.zeros((ns, m, HIST_W), dtype=torch.float64, device=bs[0].device) if record else None
+    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0,
+             _launch(block, grid, fpe, graph, tile),
+             ctypes.c_void_p(hist.data_ptr()) if hist is not None else None, None)
+    Aa = (ctypes.c_void_p * ns)(*[A.handle.value for A in As])
+    ba = (ctypes.c_void_p * ns)(*[b.data_ptr() for b in bs])
+    xa = (ctypes.c_void_p * ns)(*[x.data_ptr() for x in xs])
+    nb = ctypes.c_size_t()
+    _check(lib.rpk_solve_batched_workspace_bytes(ns, Aa, ctypes.byref(o), ctypes.byref(nb)), "workspace")
+    ws = _workspace(nb.value, ("batch", bs[0].device.index))
+    infos = (Info * ns)()
+    code = lib.rpk_solve_batched(ns, Aa, ba, xa, ctypes.byref(o), _ptr(ws), ws.numel(), _stream(), infos)
+    if code in (1, 2, 3):
+        _check(code, "rpk_solve_batched")
+    out = [_info_dict(infos[k]) for k in range(ns)]
+    if record:
+        for k in range(ns):
+            out[k]["hist"] = hist[k]
+    return xs, out
+
+
+class Server:
+    """Request server (continuous batching) of the library: solves submitted at
+    any time are admitted by HBM footprint and advanced together on the device by
+    a worker thread; every result equals the solve of that system alone."""
+
+    def __init__(self, hbm_budget, max_slots=64, chunk=0, tol=1e-9, maxit=10000, variant=PIPELINED,
+                 dots=EXACT, block=0, fpe=0, tile=0):
+        lib = load()
+        torch.cuda.init()
+        o = Opts(float(tol), int(maxit), int(variant), int(dots), 0, _launch(block, 0, fpe, 0, tile), None, None)
+        self._opts = ServerOpts(int(hbm_budget), int(max_slots), int(chunk), o)
+        h = ctypes.c_void_p()
+        _check(lib.rpk_server_create(ctypes.byref(self._opts), ctypes.byref(h)), "rpk_server_create")
+        self.handle = h
+        self._held = {}  # ticket -> (matrix, b, x): kept alive until the result is taken
+
+    def footprint(self, A):
+        nb = ctypes.c_size_t()
+        _check(load().rpk_server_footprint(self.handle, A.handle, ctypes.byref(nb)), "footprint")
+        return nb.value
+
+    def submit(self, A, b, x):
+        """Queue A x = b (x: device tensor holding x0, overwritten with the
+        solution).  Returns the ticket, or None when the request can never fit."""
+        b, x = _dev(b), _dev(x)
+        t = ctypes.c_uint64()
+        code = load().rpk_server_submit(self.handle, A.handle, _ptr(b), _ptr(x), ctypes.byref(t))
+        if code == 9:
+            return None
+        _check(code, "rpk_server_submit")
+        self._held[t.value] = (A, b, x)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else the result dict."""
+        info = Info()
+        code = load().rpk_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(info))
+        if code == 8:
+            return None
+        _check(code, "rpk_server_poll")
+        self._held.pop(ticket, None)
+        return _info_dict(info)
+
+    def wait(self, ticket):
+        info = Info()
+        _check(load().rpk_server_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(info)), "rpk_server_wait")
+        self._held.pop(ticket, None)
+        return _info_dict(info)
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().rpk_server_get_stats(self.handle, ctypes.byref(st)), "rpk_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            code = load().rpk_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+            _check(code, "rpk_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_divsqrt(a, b):
