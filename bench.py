@@ -110,6 +110,131 @@ def profile_workload():
     print("profile workload done", flush=True)
 
 
+def batched_leg(torch, rpk, inputs, reps=3):
+    """256 independent systems (half Poisson, half convection-diffusion with
+    Peclet U[0.1, 2], grid edges U{8..48}, x* ~ U(-1,1), b = A x*), standard exact
+    PBiCGStab, tol 1e-8, maxit 500, all in one batched solve (autotuned)."""
+    descs = inputs.batched_systems()
+    Ms, bs = [], []
+    for d in descs:
+        A, xs = inputs.build_system(d)
+        M = rpk.Matrix(*A)
+        Ms.append(M)
+        bs.append(rpk.exspmv(M, torch.tensor(xs, dtype=torch.float64, device="cuda")))
+    rows = sum(M.n for M in Ms)
+    nnz = sum(M.nnz for M in Ms)
+    xs, infos = rpk.solve_batched(Ms, bs, tol=1e-8, maxit=500)  # autotuner + graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xs, infos = rpk.solve_batched(Ms, bs, tol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    iters = [i["iters"] for i in infos]
+    # the same systems one after the other, each alone
+    rpk.solve(Ms[0], bs[0], tol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    same = True
+    for k, (M, b) in enumerate(zip(Ms, bs)):
+        xa, ia = rpk.solve(M, b, tol=1e-8, maxit=500)
+        if k % 37 == 0:
+            same = same and ia["iters"] == infos[k]["iters"] and bool(torch.equal(xa, xs[k]))
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t1
+    ok = all(i["status"] == "OK" for i in infos)
+    for M in Ms:
+        M.close()
+    return {"systems": len(infos), "rows": rows, "nnz": nnz, "all_converged": ok,
+            "solves_per_s": round(len(infos) / dt, 1), "ms_per_batch": round(1e3 * dt, 2),
+            "iters_min_max": [min(iters), max(iters)], "iters_total": int(sum(iters)),
+            "alone_solves_per_s": round(len(infos) / t_alone, 1),
+            "sampled_results_equal_alone": same, "launch": infos[0]["used"]}
+
+
+def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, seed=2024):
+    """Open-loop Poisson arrivals of exact pipelined solves (tol 1e-9, maxit
+    10000) on the request server; n log-uniform in [4096, 2.1M] (grid edge =
+    round(n^(1/3)) clamped to [16, 128]), Poisson or convection-diffusion (Peclet
+    U[0.1, 2]) from a seeded pool of matrices, right-hand side U(-1, 1) seeded by
+    the request id.  The arrival rate is `load` x the closed-loop saturation rate."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(pool_size):
+        n = float(np.exp(rng.uniform(np.log(4096), np.log(2.1e6))))
+        edge = int(min(128, max(16, round(n ** (1 / 3)))))
+        if k % 2 == 0:
+            A = inputs.poisson7(edge)
+        else:
+            pe = float(rng.uniform(0.1, 2.0))
+            A = inputs.convdiff7(edge, (pe, pe / 2, pe / 4))
+        pool.append(rpk.Matrix(*A))
+    pick = rng.integers(0, pool_size, size=warm + n_req + 64)
+    srv = rpk.Server(hbm_budget=2 << 30, max_slots=64, chunk=4, tol=1e-9, maxit=10000, variant=rpk.PIPELINED)
+
+    def request(r):
+        M = pool[int(pick[r])]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(10_000 + r)
+        b = torch.rand(M.n, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
+        return M, b, torch.zeros(M.n, dtype=torch.float64, device="cuda")
+
+    # closed-loop saturation: 64 requests at once
+    reqs = [request(warm + n_req + k) for k in range(64)]
+    t0 = time.perf_counter()
+    ts = [srv.submit(M, b, x) for M, b, x in reqs]
+    for t in ts:
+        srv.wait(t)
+    mu = 64 / (time.perf_counter() - t0)
+    lam = load * mu
+    gaps = rng.exponential(1.0 / lam, size=warm + n_req)
+    arrivals = np.cumsum(gaps)
+    out = {}
+    keep = {}
+    t_start = time.perf_counter()
+    r = 0
+    lat, qms, done_t = [], [], []
+    check = None
+    while r < warm + n_req or out:
+        now = time.perf_counter() - t_start
+        while r < warm + n_req and arrivals[r] <= now:
+            M, b, x = request(r)
+            out[srv.submit(M, b, x)] = (r, M, b, x)
+            r += 1
+        for t in list(out):
+            res = srv.poll(t)
+            if res is None:
+                continue
+            rid, M, b, x = out.pop(t)
+            if rid >= warm:
+                lat.append(res["latency_ms"])
+                qms.append(res["queue_ms"])
+                done_t.append(time.perf_counter() - t_start)
+                if check is None and res["iters"] > 20:
+                    check = (M, b, x.clone(), res)
+        time.sleep(0.0002)
+    span = max(done_t) - arrivals[warm]
+    st = srv.stats()
+    srv.close()
+    same = None
+    if check is not None:
+        M, b, x, res = check
+        xa, ia = rpk.solve(M, b, tol=1e-9, maxit=10000, variant=rpk.PIPELINED)
+        same = ia["iters"] == res["iters"] and bool(torch.equal(xa, x))
+    for M in pool:
+        M.close()
+    lat = np.array(lat)
+    return {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
+            "offered_solves_per_s": round(lam, 1), "solves_per_s": round(n_req / span, 1),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)), 2),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)), 2),
+            "queue_ms_p50": round(float(np.percentile(qms, 50)), 2),
+            "queue_ms_p99": round(float(np.percentile(qms, 99)), 2),
+            "hbm_budget_GiB": 2, "bytes_peak_GiB": round(st["bytes_peak"] / 2 ** 30, 2),
+            "rounds": st["rounds"], "sampled_result_equals_alone": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +243,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile", action="store_true", help="run the fixed counter-collection workload only")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched and serving legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -214,6 +340,11 @@ def main():
         "phase_us": phase,
         "roofline": roofline,
     }
+    if not args.no_batched:
+        log("batched leg ...")
+        result["batched"] = batched_leg(torch, rpk, inputs)
+        log("serving leg ...")
+        result["serving"] = serving_leg(torch, rpk, inputs)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(A, args.cpu_iters)

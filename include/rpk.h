@@ -214,8 +214,11 @@ rpk_status rpk_server_footprint(const rpk_server* s, const rpk_matrix* A, size_t
 
 /* Queue the solve of A x = b (x holds x0 on entry and the solution at the end;
  * b and x are device pointers borrowed until the request has finished; A must
- * outlive it).  *ticket identifies the request.  RPK_REJECTED: its footprint
- * exceeds the whole budget (nothing queued). */
+ * outlive it).  The server works on a stream of its own: b and x0 must already
+ * be in place (work that writes them completed) when this is called; x is
+ * complete when poll/wait report the request finished.  *ticket identifies the
+ * request.  RPK_REJECTED: its footprint exceeds the whole budget (nothing
+ * queued). */
 rpk_status rpk_server_submit(rpk_server* s, const rpk_matrix* A, const double* b, double* x, uint64_t* ticket);
 
 /* RPK_PENDING while the request runs or waits; once finished, fills *info

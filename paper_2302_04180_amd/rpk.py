@@ -310,6 +310,7 @@ class Server:
         """Queue A x = b (x: device tensor holding x0, overwritten with the
         solution).  Returns the ticket, or None when the request can never fit."""
         b, x = _dev(b), _dev(x)
+        torch.cuda.current_stream().synchronize()  # b and x0 in place before the server's stream reads them
         t = ctypes.c_uint64()
         code = load().rpk_server_submit(self.handle, A.handle, _ptr(b), _ptr(x), ctypes.byref(t))
         if code == 9:
