@@ -5,8 +5,8 @@
 // of one system; a phase launch walks the tile table (workgroup b takes tiles
 // b, b + gridDim.x, ...) and runs the same phase bodies as the single-system
 // kernels on each tile, publishing the tile's record into its own system's
-// slots.  One finishing workgroup per system then rounds that system's dot
-// products and takes its scalar step.  Every system therefore computes exactly
+// slots; the workgroup that finishes a system's last tile rounds that system's
+// dot products and takes its scalar step.  Every system therefore computes exactly
 // what it computes alone: batching changes which workgroup handles which rows,
 // and the exact reductions make that invisible in the results.
 //
@@ -49,16 +49,6 @@ __device__ __forceinline__ void tile_loop(const Batch& B, const Shm<N>& s, int b
     if (CHECK && D.V.st->done) continue;
     if (K > 0) shm_init(s, K);
     body(D, Range{T.lo, T.hi}, T.rec);
-    __syncthreads();
-  }
-}
-
-template <int N, int K, int F>
-__device__ __forceinline__ void fin_loop(const Batch& B, const Shm<N>& s, int b, int G) {
-  const int ns = B.count[1];
-  for (int k = b; k < ns; k += G) {
-    const SysDesc& D = B.sys[B.order[k]];
-    finish_body<N, K, F>(D.V, D.red, s);
     __syncthreads();
   }
 }
@@ -168,13 +158,6 @@ __global__ void __launch_bounds__(1024) kb_resid(Batch B) {
   });
 }
 
-template <int N, int K, int F>
-__global__ void __launch_bounds__(1024) kb_finish(Batch B) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, K, false);
-  fin_loop<N, K, F>(B, s, blockIdx.x, gridDim.x);
-}
-
 // ---------------------------------------------------------------------------
 // pipelined loop
 // ---------------------------------------------------------------------------
@@ -214,18 +197,12 @@ __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   });
 }
 
-// SpMV of the pipelined loop over all tiles || the pending reduction of every
-// system: workgroups 0 .. Gf-1 finish systems, the others walk the tiles.
-// W selects the product: 0: t = A w^ (set-up 3, S18), 1: v = A z^ (S10).
-template <int N, int K, int F, int W, bool CHECK>
-__global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B, int Gf) {
+// SpMVs of the pipelined loop over all tiles: W = 0: t = A w^, 1: v = A z^.
+template <int N, int W>
+__global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B) {
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, K, true);
-  if ((int)blockIdx.x < Gf) {
-    fin_loop<N, K, F>(B, s, blockIdx.x, Gf);
-    return;
-  }
-  tile_loop<N, 0, CHECK>(B, s, blockIdx.x - Gf, gridDim.x - Gf, [&](const SysDesc& D, Range R, int) {
+  Shm<N> s = shm_carve<N>(smem, 0, true);
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int) {
     if (W == 0) spmv_body<N>(D.A, D.V.wh, D.V.t, R, s);
     else spmv_body<N>(D.A, D.V.zh, D.V.v, R, s);
   });

@@ -4,8 +4,8 @@
 //
 // Workspace (256-byte aligned pieces):
 //   header : tile/system counts | States[nsys] | SysDesc[nsys] | order[nsys] | Tile[cap]
-//   per system k: tickets+flags | long accumulators | window records (cap_k
-//                 tiles) | solver vectors
+//   per system k: tickets+flags | long accumulators | plain-mode tile sums
+//                 (cap_k tiles) | solver vectors
 //   trial  : one x per system (only when the autotuner may run)
 // The header is written with one host-to-device copy per call; everything the
 // kernels need is found through it, so a cached graph only depends on the
@@ -83,7 +83,7 @@ int64_t tile_capacity(const std::vector<int64_t>& n, int Tcap) {
 }
 
 size_t sys_bytes(int64_t n, int gcap, int nvec) {
-  return up(kFlagsBytes) + up((size_t)MAX_DOTS * SA_D * 8) + up((size_t)MAX_DOTS * REC * gcap * 8) +
+  return up(kFlagsBytes) + up((size_t)MAX_DOTS * SA_D * 8) + up((size_t)MAX_DOTS * gcap * 8) +
          (size_t)nvec * up((size_t)n * 8);
 }
 
@@ -95,7 +95,7 @@ SysDesc make_desc(const rpk_matrix* A, const double* b, double* x, char* base, i
   r.gsa = (long long*)(base + up(kFlagsBytes));
   r.partials = (double*)(base + up(kFlagsBytes) + up((size_t)MAX_DOTS * SA_D * 8));
   r.G = G;
-  char* vec = (char*)r.partials + up((size_t)MAX_DOTS * REC * gcap * 8);
+  char* vec = (char*)r.partials + up((size_t)MAX_DOTS * gcap * 8);
   const size_t step = up((size_t)A->n * 8);
   double* p[16];
   for (int j = 0; j < nvec_of(variant); ++j) p[j] = (double*)(vec + j * step);
@@ -252,7 +252,7 @@ Shape shape_of(const Ctx& c, const BCfg& cfg, const Plan& plan) {
   sh.Gf = std::min((c.ns + 7) & ~7, 1024);
   sh.B = cfg.block;
   sh.N = (c.o->dots == RPK_DOT_PLAIN) ? 0 : cfg.fpe;
-  sh.nph = (c.o->variant == RPK_STD) ? 8 : 4;
+  sh.nph = (c.o->variant == RPK_STD) ? 5 : 4;
   return sh;
 }
 

@@ -444,21 +444,26 @@ template <int N>
 __device__ __forceinline__ void acc_prod(Fpe<N>& f, double a, double b, long long* sa, int* flag) {
   const double p = a * b;
   const double ap = fabs(p);
-  if (ap >= kProdLo && ap < kProdHi) {
-    const double e = fma(a, b, -p);
-    const double l1 = fpe_add_w<N, 0>(f, p);
-    const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
+  // common case without per-lane branches: out-of-range products insert 0 here
+  // and are handled below
+  const bool ok = ap >= kProdLo && ap < kProdHi;
+  const double e = ok ? fma(a, b, -p) : 0.0;
+  const double l1 = fpe_add_w<N, 0>(f, ok ? p : 0.0);
+  const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
+  const bool extreme = !ok && !(p == 0.0 && (a == 0.0 || b == 0.0));
+  if (l1 != 0.0 || l2 != 0.0 || extreme) {
     if (l1 != 0.0 || l2 != 0.0) {
       sa_add_double(sa, l1);
       sa_add_double(sa, l2);
       atomicOr(flag, F_SA);
     }
-  } else if (!(p == 0.0 && (a == 0.0 || b == 0.0))) {
-    if (!isfinite(a) || !isfinite(b)) {
-      atomicOr(flag, F_NONFINITE);
-    } else {
-      sa_add_prod(sa, a, b);
-      atomicOr(flag, F_SA);
+    if (extreme) {
+      if (!isfinite(a) || !isfinite(b)) {
+        atomicOr(flag, F_NONFINITE);
+      } else {
+        sa_add_prod(sa, a, b);
+        atomicOr(flag, F_SA);
+      }
     }
   }
 }

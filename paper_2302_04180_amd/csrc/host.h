@@ -65,8 +65,8 @@ Plan make_plan(const std::vector<int64_t>& n, int T, const std::vector<int>* ids
 // upper bound of make_plan(n, T).tiles.size() for every T >= Tcap
 int64_t tile_capacity(const std::vector<int64_t>& n, int Tcap);
 
-// Device block of one system: tickets + flags | long accumulators | window
-// records for gcap tiles | nvec solver vectors of n doubles.
+// Device block of one system: tickets + flags | long accumulators | plain-mode
+// sums of gcap tiles | nvec solver vectors of n doubles.
 constexpr size_t kFlagsBytes = 8 * sizeof(unsigned) + MAX_DOTS * sizeof(int);
 size_t sys_bytes(int64_t n, int gcap, int nvec);
 // Descriptor of a system whose block starts at `base` (device address).

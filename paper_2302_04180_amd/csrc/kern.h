@@ -26,7 +26,7 @@ struct Kern {
 };
 
 // Batched launchers: G = workgroups of the tile-walking kernels, Gf = workgroups
-// of the finishing kernels (and of the finishing part of the pipelined SpMVs).
+// of the per-system set-up kernel.
 template <int N>
 struct KernB {
   static rpk_status setup(int Gf, hipStream_t s, Batch b, double tol, int maxit, int variant);

@@ -10,13 +10,10 @@ static rpk_status launch(K kernel, int grid, int block, size_t shm, hipStream_t 
   return hipGetLastError() == hipSuccess ? RPK_OK : RPK_ERR_HIP;
 }
 
-constexpr int FB = 1024;  // workgroup size of the one-workgroup finishing kernels
-
 template <int N>
 rpk_status Kern<N>::dot(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* out,
                         Red red) {
-  RET_IF(launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, red));
-  return launch(k_dot_finish<N>, 1, FB, shm_bytes(N, 1, false, FB), s, out, red);
+  return launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, out, red);
 }
 
 template <int N>
@@ -26,19 +23,15 @@ rpk_status Kern<N>::spmv(int G, int B, hipStream_t s, Csr A, const double* x, do
 
 template <int N>
 rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
-  if (variant == RPK_STD) {
-    RET_IF(launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-    return launch(k_finish<N, 1, FIN_ENTRY>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
-  }
+  if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-  return launch(k_pipe_init3<N>, G + 1, B, shm_bytes(N, 2, true, B), s, A, V, red);
+  return launch(k_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, A, V);
 }
 
 template <int N>
 rpk_status Kern<N>::resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
-  RET_IF(launch(k_resid<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-  return launch(k_finish<N, 1, FIN_RESID>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
+  return launch(k_resid<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
 }
 
 template <int N>
@@ -47,19 +40,16 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
     switch (ph) {
       case 0: return launch(k_std_A<N>, G, B, 0, s, A, V);
       case 1: return launch(k_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 2: return launch(k_finish<N, 1, FIN_ALPHA>, 1, FB, shm_bytes(N, 1, false, FB), s, V, red);
-      case 3: return launch(k_std_C<N>, G, B, 0, s, A, V);
-      case 4: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
-      case 5: return launch(k_finish<N, 2, FIN_OMEGA>, 1, FB, shm_bytes(N, 2, false, FB), s, V, red);
-      case 6: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
-      default: return launch(k_finish<N, 2, FIN_BETA>, 1, FB, shm_bytes(N, 2, false, FB), s, V, red);
+      case 2: return launch(k_std_C<N>, G, B, 0, s, A, V);
+      case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
+      default: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
     }
   }
   switch (ph) {
     case 0: return launch(k_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
-    case 1: return launch(k_pipe_P2<N>, G + 1, B, shm_bytes(N, 2, true, B), s, A, V, red);
+    case 1: return launch(k_pipe_spmv<N, 1>, G, B, shm_bytes(N, 0, true, B), s, A, V);
     case 2: return launch(k_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, A, V, red);
-    default: return launch(k_pipe_P4<N>, G + 1, B, shm_bytes(N, 5, true, B), s, A, V, red);
+    default: return launch(k_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, A, V);
   }
 }
 
@@ -72,40 +62,36 @@ rpk_status KernB<N>::setup(int Gf, hipStream_t s, Batch b, double tol, int maxit
 
 template <int N>
 rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batch b) {
-  if (variant == RPK_STD) {
-    RET_IF(launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-    return launch(kb_finish<N, 1, FIN_ENTRY>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
-  }
+  (void)Gf;
+  if (variant == RPK_STD) return launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b);
   RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
   RET_IF(launch(kb_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-  return launch(kb_pipe_spmv<N, 2, FIN_PENTRY, 0, false>, Gf + G, B, shm_bytes(N, 2, true, B), s, b, Gf);
+  return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
 }
 
 template <int N>
 rpk_status KernB<N>::resid(int G, int Gf, int B, hipStream_t s, Batch b) {
-  RET_IF(launch(kb_resid<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-  return launch(kb_finish<N, 1, FIN_RESID>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
+  (void)Gf;
+  return launch(kb_resid<N>, G, B, shm_bytes(N, 1, true, B), s, b);
 }
 
 template <int N>
 rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_t s, Batch b) {
+  (void)Gf;
   if (variant == RPK_STD) {
     switch (ph) {
       case 0: return launch(kb_std_A<N>, G, B, 0, s, b);
       case 1: return launch(kb_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, b);
-      case 2: return launch(kb_finish<N, 1, FIN_ALPHA>, Gf, FB, shm_bytes(N, 1, false, FB), s, b);
-      case 3: return launch(kb_std_C<N>, G, B, 0, s, b);
-      case 4: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
-      case 5: return launch(kb_finish<N, 2, FIN_OMEGA>, Gf, FB, shm_bytes(N, 2, false, FB), s, b);
-      case 6: return launch(kb_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, b);
-      default: return launch(kb_finish<N, 2, FIN_BETA>, Gf, FB, shm_bytes(N, 2, false, FB), s, b);
+      case 2: return launch(kb_std_C<N>, G, B, 0, s, b);
+      case 3: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
+      default: return launch(kb_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, b);
     }
   }
   switch (ph) {
     case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, b);
-    case 1: return launch(kb_pipe_spmv<N, 2, FIN_POMEGA, 1, true>, Gf + G, B, shm_bytes(N, 2, true, B), s, b, Gf);
+    case 1: return launch(kb_pipe_spmv<N, 1>, G, B, shm_bytes(N, 0, true, B), s, b);
     case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, b);
-    default: return launch(kb_pipe_spmv<N, 5, FIN_S19, 0, true>, Gf + G, B, shm_bytes(N, 5, true, B), s, b, Gf);
+    default: return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
   }
 }
 

@@ -19,13 +19,11 @@ constexpr int HIST_W = 12;   // doubles per recorded iteration
 constexpr int MAX_DOTS = 8;  // reduction slots in the workspace
 // Exact cross-lane reduction: each workgroup sums its lanes' FPE components as
 // integers in a window of WIN digits of the long-accumulator grid, anchored at
-// the workgroup's leading digit; the finishing workgroup aligns the G windows in
-// a window of WG digits anchored at the overall leading digit.  Digits that fall
-// below a window (data spread over more than ~350 / ~900 bits) go to the long
-// accumulator, so nothing is ever dropped.
+// the workgroup's leading digit, and adds the window into the dot's global long
+// accumulator.  Digits that fall below the window (data spread over more than
+// ~350 bits) go to the long accumulator directly, so nothing is ever dropped.
 constexpr int WIN = 12;
-constexpr int WG = 32;
-constexpr int REC = 16;                       // int64 words per workgroup record: [0] base digit, [1..WIN]
+constexpr int REC = 16;                        // int64 words of a window record: [0] base digit, [1..WIN]
 constexpr long long REC_EMPTY = -(1ll << 40);  // record of a workgroup whose sum is zero
 
 enum : int { ST_OK = 0, ST_NONFINITE = 5, ST_NOT_CONVERGED = 6, ST_BREAKDOWN = 7 };
@@ -52,13 +50,13 @@ struct State {
   int variant, pad0, pad1, pad2;
 };
 
-// Reduction scratch in the caller's workspace.
+// Reduction scratch in the caller's workspace (left zeroed after every use).
 struct Red {
-  double* partials;    // exact: records [slot][G][REC] (int64); plain: [slot][G] doubles
-  long long* gsa;      // [slot][SA_D] long accumulators (left zeroed by consumers)
-  int* gflags;         // [slot]      (left zeroed by consumers)
-  unsigned* tickets;   // [8]         (left zeroed by the last block)
-  int G;               // number of partial-producing workgroups
+  double* partials;    // plain mode: [slot][G] workgroup sums
+  long long* gsa;      // [slot][SA_D] global long accumulators
+  int* gflags;         // [slot]
+  unsigned* tickets;   // [8] arrival counters
+  int G;               // number of workgroups (or tiles) that publish
 };
 
 // ---------------------------------------------------------------------------
@@ -71,24 +69,26 @@ __host__ __device__ inline size_t shm_bytes(int N, int K, bool rows, int block) 
   (void)rows;
   const size_t nw = (size_t)block / 64;
   const size_t sa = (N > 0) ? (size_t)K * SA_D * 8 : 0;
-  // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D) and
-  // the finisher's per-wave accumulators use the same space at other times
+  // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D)
+  // use the same space at other times
   const size_t scat = (N > 0) ? nw * scat_rows(block) * WIN * 8 : 0;
   const size_t wsum = (N > 0) ? 16 * WIN * 8 : 0;
-  return sa + scat + wsum + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
+  const size_t wrec = (N > 0) ? MAX_DOTS * REC * 8 : 0;
+  return sa + scat + wsum + wrec + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
 }
 
 template <int N>
 struct Shm {
   long long* sa;    // K * SA_D    long accumulators (rare path)
   long long* wsa;   // nw * SA_D   row fallback accumulators (aliases scat)
-  long long* scat;  // nw * rows * WIN scatter rows; also the finisher's per-wave accumulators
+  long long* scat;  // nw * rows * WIN scatter rows
   long long* wsum;  // 16 * WIN    per-wave window sums
+  long long* wrec;  // MAX_DOTS * REC  window records of this workgroup
   double* pbuf;     // 16          plain per-wave sums
   int* imax;        // 16 * MAX_DOTS per-wave maxima
   double* res;      // MAX_DOTS
   int* flag;        // MAX_DOTS
-  int* misc;        // 4 + MAX_DOTS
+  int* misc;        // 4 + MAX_DOTS  ([1..K] flags, [10] last-arrival, [11] sink)
 };
 
 template <int N>
@@ -104,6 +104,8 @@ __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
   off += (N > 0) ? nw * scat_rows(blockDim.x) * WIN * 8 : 0;
   s.wsum = (long long*)(base + off);
   off += (N > 0) ? 16 * WIN * 8 : 0;
+  s.wrec = (long long*)(base + off);
+  off += (N > 0) ? MAX_DOTS * REC * 8 : 0;
   s.pbuf = (double*)(base + off);
   off += 16 * 8;
   s.imax = (int*)(base + off);
@@ -202,14 +204,12 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
     for (int u = 0; u < 8; ++u) {
       const double p = a[u] * b[u];
       const double ap = fabs(p);
-      if (ap >= kProdLo && ap < kProdHi) {
-        const double e = fma(a[u], b[u], -p);
-        const double l1 = fpe_add_w<N, 0>(f, p);
-        const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
-        ovf |= (l1 != 0.0) | (l2 != 0.0);
-      } else if (!(p == 0.0 && (a[u] == 0.0 || b[u] == 0.0))) {
-        ovf = true;
-      }
+      // no per-lane branch: an out-of-range product inserts 0 and flags the row
+      const bool okp = ap >= kProdLo && ap < kProdHi;
+      const double e = okp ? fma(a[u], b[u], -p) : 0.0;
+      const double l1 = fpe_add_w<N, 0>(f, okp ? p : 0.0);
+      const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
+      ovf |= (l1 != 0.0) | (l2 != 0.0) | (!okp && !(p == 0.0 && (a[u] == 0.0 || b[u] == 0.0)));
     }
   }
   bad = ovf;
@@ -416,32 +416,59 @@ __device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, l
   __syncthreads();
 }
 
-// Publish the K dots of this workgroup (records or plain partials) to slots
-// slot0..slot0+K-1; rare long-accumulator content goes to the global ones.
-// `b` is the record index of this workgroup (0 <= b < red.G).
+// ---------------------------------------------------------------------------
+// Cross-workgroup reduction, finished by the last workgroup to arrive
+// ---------------------------------------------------------------------------
+// Every workgroup adds its part of each dot product into that dot's global long
+// accumulator with device-scope integer atomics (its exact window digits, plus
+// whatever went to its own long accumulator) and waits for their returned
+// values, i.e. until they have been performed at the device's point of
+// coherence.  Only then does it draw a ticket.  The workgroup that draws the last
+// ticket reads and clears the accumulators with device-scope atomic exchanges,
+// which observe every addition performed before, and rounds them.  No cache
+// write-back fence is needed, and integer addition is associative, so the order
+// of arrival cannot change the sum.  Plain FP64 mode: each workgroup publishes
+// its block sum into its own slot the same way and the last one adds the G sums
+// in workgroup order.
+__device__ __forceinline__ unsigned long long dev_add(long long* p, long long v) {
+  return __hip_atomic_fetch_add((unsigned long long*)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true (in every thread) in the last workgroup to arrive.  `ticket`
+// selects the arrival counter (kernels that run one after the other may share).
 template <int N, int K>
-__device__ __forceinline__ void block_publish(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0, int b) {
+__device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0,
+                                                   int b, int ticket) {
+  const int tid = threadIdx.x;
+  unsigned long long sink = 0;
   if constexpr (N > 0) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      long long* rec = (long long*)red.partials + ((size_t)(slot0 + j) * red.G + b) * REC;
-      block_window(d[j].f, s, s.sa + (size_t)j * SA_D, &s.flag[j], rec);
-    }
+    for (int j = 0; j < K; ++j) block_window(d[j].f, s, s.sa + (size_t)j * SA_D, &s.flag[j], s.wrec + j * REC);
     __syncthreads();
-    if (threadIdx.x < 64) {
+    // window digits: thread t < K * WIN adds digit t % WIN of dot t / WIN
+    if (tid < K * WIN) {
+      const int j = tid / WIN, k = tid % WIN;
+      const long long base = s.wrec[j * REC];
+      const long long v = s.wrec[j * REC + 1 + k];
+      const long long g = base + k;
+      if (base != REC_EMPTY && v != 0 && g >= 0 && g < SA_D)
+        sink += dev_add(red.gsa + (size_t)(slot0 + j) * SA_D + g, v);
+    }
+    // rare: this workgroup's own long accumulators, and the non-finite flags
+    if (tid < 64) {
       for (int j = 0; j < K; ++j) {
         const int fl = s.flag[j];
-        if (fl & F_NONFINITE) {
-          if (threadIdx.x == 0) atomicOr(&red.gflags[slot0 + j], F_NONFINITE);
-        }
+        if ((fl & F_NONFINITE) && tid == 0)
+          sink += (unsigned)__hip_atomic_fetch_or(&red.gflags[slot0 + j], F_NONFINITE, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
         if (fl & F_SA) {
           long long* sa = s.sa + (size_t)j * SA_D;
           int lo, hi;
           sa_normalize_wave(sa, lo, hi);
           long long* g = red.gsa + (size_t)(slot0 + j) * SA_D;
-          for (int k = lo + (int)threadIdx.x; k <= hi; k += 64)
-            if (sa[k]) atomicAdd((unsigned long long*)&g[k], (unsigned long long)sa[k]);
-          if (threadIdx.x == 0) atomicOr(&red.gflags[slot0 + j], F_SA);
+          for (int k = lo + tid; k <= hi; k += 64)
+            if (sa[k]) sink += dev_add(g + k, sa[k]);
         }
       }
     }
@@ -449,131 +476,76 @@ __device__ __forceinline__ void block_publish(Dot<N> (&d)[K], const Shm<N>& s, c
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const double v = plain_block_sum(d[j].s, s.pbuf);
-      if (threadIdx.x == 0) red.partials[(size_t)(slot0 + j) * red.G + b] = v;
+      if (tid == 0)
+        sink += __hip_atomic_exchange((unsigned long long*)&red.partials[(size_t)(slot0 + j) * red.G + b],
+                                      (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-}
-
-// Record words a finishing workgroup loads before anything else (the first
-// FIN_PRE rounds of 16-thread-per-record loads of every dot).
-constexpr int FIN_PRE = 4;
-template <int N, int K>
-struct FinPre {
-  long long v[K > 0 ? K : 1][FIN_PRE];
-  int gfl;
-};
-
-template <int N, int K>
-__device__ __forceinline__ void fin_prefetch(FinPre<N, K>& pre, const Red& red, int slot0) {
-  if constexpr (N > 0) {
-    const int tid = threadIdx.x, rstep = blockDim.x >> 4, word = tid & 15;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const long long* recs = (const long long*)red.partials + (size_t)(slot0 + j) * red.G * REC;
-#pragma unroll
-      for (int q = 0; q < FIN_PRE; ++q) {
-        const int r = (tid >> 4) + q * rstep;
-        pre.v[j][q] = (r < red.G) ? recs[(size_t)r * REC + word] : 0ll;
-      }
-    }
-    pre.gfl = (tid < K) ? red.gflags[slot0 + tid] : 0;
+  // using the returned values makes every thread wait until its atomics have
+  // been performed before the barrier that precedes the ticket
+  if (sink == 0x5bd1e9955bd1e995ull) s.misc[11] = 1;
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned t = __hip_atomic_fetch_add(&red.tickets[ticket], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = (t == (unsigned)red.G - 1u);
+    if (last) __hip_atomic_exchange(&red.tickets[ticket], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s.misc[10] = last;
   }
+  __syncthreads();
+  return s.misc[10] != 0;
 }
 
-// One workgroup rounds the K dots of slots slot0.. into s.res[0..K-1] and
-// clears the global long accumulators and flags it consumed.  Per dot: one
-// round of coalesced loads of all record words (16 threads per record); each
-// digit is added with an LDS integer atomic into its wave's accumulator at its
-// absolute grid position, so no alignment pass is needed; the waves' sums (plus
-// the global long accumulator when used) are added digit-wise, and the value is
-// rounded from a 32-digit register window at its lowest non-zero digit.
+// In the last workgroup: round the K dots of slots slot0.. into s.res[0..K-1],
+// leaving the accumulators, flags (and plain slots) for the next use.
 template <int N, int K>
-__device__ __forceinline__ void block_finalize(const Shm<N>& s, const Red& red, int slot0,
-                                               const FinPre<N, K>* pre = nullptr) {
+__device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& red, int slot0) {
+  const int tid = threadIdx.x, bd = blockDim.x;
   if constexpr (N > 0) {
-    FinPre<N, K> own;
-    if (pre == nullptr) {
-      fin_prefetch(own, red, slot0);
-      pre = &own;
+    for (int i = tid; i < K * SA_D; i += bd) {
+      const int j = i / SA_D, k = i - j * SA_D;
+      s.sa[i] = (long long)__hip_atomic_exchange((unsigned long long*)&red.gsa[(size_t)(slot0 + j) * SA_D + k], 0ull,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const int tid = threadIdx.x, bd = blockDim.x, nw = bd >> 6, w = tid >> 6, lane = tid & 63;
-    const int G = red.G;
-    if (tid < K) s.misc[1 + tid] = pre->gfl;
-    long long* acc = s.scat + (size_t)w * SA_D;  // this wave's accumulator (scatter area >= nw * SA_D)
-    const int word = tid & 15, rstep = bd >> 4;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const long long* recs = (const long long*)red.partials + (size_t)(slot0 + j) * G * REC;
-      for (int k = lane; k < SA_D; k += 64) acc[k] = 0;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      long long pv[FIN_PRE];  // pre->v[j] with static indices only (no private-memory array)
-#pragma unroll
-      for (int q = 0; q < FIN_PRE; ++q) pv[q] = pre->v[0][q];
-#pragma unroll
-      for (int jj = 1; jj < K; ++jj)
-        if (jj == j)
-#pragma unroll
-          for (int q = 0; q < FIN_PRE; ++q) pv[q] = pre->v[jj][q];
-#pragma unroll
-      for (int q = 0; q < FIN_PRE; ++q) {
-        const long long v = pv[q];
-        const long long base = __shfl(v, lane & ~15, 64);
-        const int r = (tid >> 4) + q * rstep;
-        if (r < G && word >= 1 && word <= WIN && v != 0 && base != REC_EMPTY)
-          atomicAdd((unsigned long long*)&acc[base + word - 1], (unsigned long long)v);
-      }
-#pragma unroll 4
-      for (int r = (tid >> 4) + FIN_PRE * rstep; r < G; r += rstep) {
-        const long long v = recs[(size_t)r * REC + word];
-        const long long base = __shfl(v, lane & ~15, 64);
-        if (word >= 1 && word <= WIN && v != 0 && base != REC_EMPTY)
-          atomicAdd((unsigned long long*)&acc[base + word - 1], (unsigned long long)v);
-      }
-      __syncthreads();
+    if (tid < K)
+      s.misc[1 + tid] = __hip_atomic_exchange(&red.gflags[slot0 + tid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
+    for (int j = w; j < K; j += nw) {  // one wave per dot
       long long* tot = s.sa + (size_t)j * SA_D;
-      const bool use_g = (s.misc[1 + j] & F_SA) != 0;
-      long long* g = red.gsa + (size_t)(slot0 + j) * SA_D;
-      for (int k = tid; k < SA_D; k += bd) {
-        long long v = 0;
-        for (int i = 0; i < nw; ++i) v += s.scat[(size_t)i * SA_D + k];
-        if (use_g) {
-          v += g[k];
-          g[k] = 0;
+      int lo, hi;
+      wave_digit_range(tot, SA_D, lo, hi);
+      double r = 0.0;
+      if (hi >= 0) {
+        constexpr int RW = 16;  // register window (digits) of the common case
+        const int start = (lo < SA_D - RW) ? lo : SA_D - RW;
+        if (hi + 2 <= start + RW - 1) {
+          if (lane == 0) r = window_round_reg<RW>(tot + start, start);
+        } else {
+          r = sa_round_wave(tot);
         }
-        tot[k] = v;
       }
-      __syncthreads();
-      if (tid < 64) {
-        int lo, hi;
-        wave_digit_range(tot, SA_D, lo, hi);
-        double r = 0.0;
-        if (hi >= 0) {
-          constexpr int RW = 16;  // register window (digits) of the common case
-          const int start = (lo < SA_D - RW) ? lo : SA_D - RW;
-          if (hi + 2 <= start + RW - 1) {
-            if (tid == 0) r = window_round_reg<RW>(tot + start, start);
-          } else {
-            r = sa_round_wave(tot);
-          }
-        }
-        if (tid == 0) s.res[j] = r;
-      }
-      __syncthreads();
-    }
-    if (tid < K) {
-      if (s.misc[1 + tid] & F_NONFINITE) s.res[tid] = __longlong_as_double(0x7ff8000000000000ll);
-      if (s.misc[1 + tid]) red.gflags[slot0 + tid] = 0;
+      if (lane == 0) s.res[j] = r;
     }
     __syncthreads();
+    if (tid < K && (s.misc[1 + tid] & F_NONFINITE)) s.res[tid] = __longlong_as_double(0x7ff8000000000000ll);
+    __syncthreads();
   } else {
+    double v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = 0.0;
+    for (int b = tid; b < red.G; b += bd)  // the loads of all K dots in flight together
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        v[j] += __longlong_as_double((long long)__hip_atomic_load(
+            (unsigned long long*)&red.partials[(size_t)(slot0 + j) * red.G + b], __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT));
+#pragma unroll
     for (int j = 0; j < K; ++j) {
-      double v = 0.0;
-      for (int b = threadIdx.x; b < red.G; b += blockDim.x) v += red.partials[(size_t)(slot0 + j) * red.G + b];
-      v = plain_block_sum(v, s.pbuf);
-      if (threadIdx.x == 0) s.res[j] = v;
-      __syncthreads();
+      const double t = plain_block_sum(v[j], s.pbuf);
+      if (tid == 0) s.res[j] = t;
     }
+    __syncthreads();
   }
 }
 
@@ -582,7 +554,7 @@ __device__ __forceinline__ void block_finalize(const Shm<N>& s, const Red& red, 
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(1024) k_dot(long long n, const double* __restrict__ x,
-                                              const double* __restrict__ y, Red red) {
+                                              const double* __restrict__ y, double* out, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, false);
   shm_init(s, 1);
@@ -595,15 +567,8 @@ __global__ void __launch_bounds__(1024) k_dot(long long n, const double* __restr
   Dot<N> d[1];
   d[0].zero();
   for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) d[0].add(x[i], y[i], s.sa, &s.flag[0]);
-  block_publish<N, 1>(d, s, red, 0, blockIdx.x);
-}
-
-template <int N>
-__global__ void __launch_bounds__(1024) k_dot_finish(double* out, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 1, false);
-  shm_init(s, 1);
-  block_finalize<N, 1>(s, red, 0);
+  if (!block_publish_last<N, 1>(d, s, red, 0, blockIdx.x, 0)) return;
+  block_finalize_last<N, 1>(s, red, 0);
   if (threadIdx.x == 0) out[0] = s.res[0];
 }
 

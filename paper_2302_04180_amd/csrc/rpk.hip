@@ -64,7 +64,7 @@ Layout layout(int grid, int64_t n, int nvec) {
   l.gsa = off;
   off += up((size_t)MAX_DOTS * SA_D * sizeof(long long));
   l.partials = off;
-  off += up((size_t)MAX_DOTS * REC * grid * sizeof(long long));
+  off += up((size_t)MAX_DOTS * grid * sizeof(double));  // plain-mode workgroup sums
   l.vecs = off;
   off += (size_t)nvec * up((size_t)n * sizeof(double));
   l.total = off;
@@ -397,7 +397,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   const int variant = o->variant;
   const int N = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
   const int G = c.grid, B = c.block;
-  const int nph = (variant == RPK_STD) ? 8 : 4;
+  const int nph = (variant == RPK_STD) ? 5 : 4;
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);

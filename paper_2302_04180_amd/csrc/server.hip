@@ -383,7 +383,7 @@ rpk_status rpk_server_create(const rpk_server_opts* o, rpk_server** out) {
   S->tile = l.tile ? l.tile : 4096;
   S->N = (so.dots == RPK_DOT_PLAIN) ? 0 : (l.fpe ? l.fpe : 4);
   S->nvec = nvec_of(so.variant);
-  S->nph = (so.variant == RPK_STD) ? 8 : 4;
+  S->nph = (so.variant == RPK_STD) ? 5 : 4;
   rpk_status st = RPK_OK;
   do {
     if (hipGetDevice(&S->device) != hipSuccess) { st = RPK_ERR_HIP; break; }

@@ -1,23 +1,23 @@
 // solver.h -- fused phase kernels of PBiCGStab (Fig. 2) and p-PBiCGStab (Fig. 3).
 //
-// Standard loop, five streaming kernels per iteration; each reduction point is
-// followed by a one-workgroup kernel that rounds the dot products and takes the
-// scalar step (no grid-wide fences: on gfx950 an agent-scope release writes
-// back the XCD's L2, which made a last-block-finishes scheme cost more than the
-// kernels).  Recomputing p^ / q^ inside the SpMV gathers instead of storing
-// them was measured slower: it multiplies the gathered vectors by 3-4.
+// Standard loop, five kernels per iteration.  Each reduction point ends a
+// kernel: the last workgroup to finish rounds the dot products and takes the
+// scalar step (kernels.h, block_publish_last), so no separate finishing kernel
+// and no grid-wide fence is needed.  Recomputing p^ / q^ inside the SpMV
+// gathers instead of storing them was measured slower: it multiplies the
+// gathered vectors by 3-4.
 //   A: S12 (from the second iteration on) + S1
-//   B: S2 SpMV (gathers p^) + S3 partials         -> finish: alpha
+//   B: S2 SpMV (gathers p^) + S3                  -> last workgroup: alpha
 //   C: S4 + S5
-//   D: S6 SpMV (gathers q^) + S7 partials         -> finish: omega
-//   E: S8 + S9, S10/S11 partials                  -> finish: tau, stop test, beta
-// Pipelined loop, four kernels per iteration; each reduction is finished by one
-// extra workgroup of the following SpMV kernel, so it overlaps that SpMV (the
-// single-GPU counterpart of the Iallreduce/Wait pairs of Sec. 4.2):
-//   P1: S1..S7 + S9 + S8 dot partials
-//   P2: S10 SpMV  || S11 omega
-//   P3: S12..S15 + S17 + S16 dot partials (and <r,r> for tau)
-//   P4: S18 SpMV  || S19 tau, stop test, beta, delta, alpha
+//   D: S6 SpMV (gathers q^) + S7                  -> last workgroup: omega
+//   E: S8 + S9, S10/S11                           -> last workgroup: tau, stop test, beta
+// Pipelined loop, four kernels per iteration.  The reductions of Fig. 3 are
+// finished at the end of the kernel that produces their terms, so on one GPU
+// there is no latency left for the SpMVs to hide:
+//   P1: S1..S7 + S9 + S8                          -> last workgroup: omega (S11)
+//   P2: S10 SpMV
+//   P3: S12..S15 + S17 + S16 (and <r,r> for tau)  -> last workgroup: S19
+//   P4: S18 SpMV
 // Every update is the explicit fma written next to it; scalar steps are single
 // IEEE operations in one thread, in the order of the figures.
 #pragma once
@@ -129,13 +129,12 @@ __device__ __forceinline__ void step_std_beta(State* st, double* h, double rho_n
   st->rho = rho_new;
 }
 
-// pipelined set-up: alpha0 = rho / <r0, w>
-__device__ __forceinline__ void step_pipe_entry(State* st, double rho, double mu) {
-  step_entry(st, rho);
+// pipelined set-up: alpha0 = rho / <r0, w> (after step_entry)
+__device__ __forceinline__ void step_pipe_alpha0(State* st, double mu) {
   if (st->done) return;
   if (isnan(mu)) return stop(st, ST_NONFINITE);
   if (mu == 0.0) return stop(st, ST_BREAKDOWN);
-  st->alpha = rho / mu;
+  st->alpha = st->rho / mu;
   st->beta = 0.0;
   st->omega = 0.0;
   step_loop_entry(st);
@@ -167,6 +166,56 @@ __device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double
   st->rho = rho_new;
 }
 
+// Reduction points: which scalar step the last workgroup takes.
+enum : int {
+  FIN_ENTRY = 0,     // <r0,r0>            -> tau0, loop entry test (standard)
+  FIN_ALPHA = 1,     // <r0,s>             -> alpha (S3)
+  FIN_OMEGA = 2,     // <q,y>, <y,y>       -> omega (S7)
+  FIN_BETA = 3,      // <r0,r>, <r,r>      -> tau, stop test, beta (S10, S11)
+  FIN_RESID = 4,     // <e,e>              -> true residual
+  FIN_PENTRY1 = 5,   // <r0,r0>            -> tau0 (pipelined set-up)
+  FIN_PENTRY2 = 6,   // <r0,w>             -> alpha0, loop entry test
+  FIN_POMEGA = 7,    // <q,y>, <y,y>       -> omega (S11 of the pipelined loop)
+  FIN_S19 = 8        // 5 dots             -> S19
+};
+
+template <int F>
+__device__ __forceinline__ void scalar_step(const Vecs& V, const double* res) {
+  State S;
+  state_load(S, V.st);
+  if constexpr (F == FIN_ENTRY) {
+    step_entry(&S, res[0]);
+    step_loop_entry(&S);
+  } else if constexpr (F == FIN_ALPHA) {
+    step_std_alpha(&S, hist_row(V, S.iter), res[0]);
+  } else if constexpr (F == FIN_OMEGA) {
+    step_omega(&S, hist_row(V, S.iter), res[0], res[1], 2);
+  } else if constexpr (F == FIN_BETA) {
+    step_std_beta(&S, hist_row(V, S.iter), res[0], res[1]);
+  } else if constexpr (F == FIN_RESID) {
+    S.true_res = sqrt(res[0]);
+  } else if constexpr (F == FIN_PENTRY1) {
+    step_entry(&S, res[0]);
+  } else if constexpr (F == FIN_PENTRY2) {
+    step_pipe_alpha0(&S, res[0]);
+  } else if constexpr (F == FIN_POMEGA) {
+    step_omega(&S, hist_row(V, S.iter), res[0], res[1], 0);
+  } else {
+    step_pipe_s19(&S, hist_row(V, S.iter), res);
+  }
+  state_store(V.st, S);
+}
+
+// Publish this workgroup's K dot partials; the last workgroup to arrive rounds
+// the dots and takes the scalar step F.
+template <int N, int K, int F>
+__device__ __forceinline__ void publish_step(Dot<N> (&d)[K], const Shm<N>& s, const Vecs& V, const Red& red,
+                                             int rec) {
+  if (!block_publish_last<N, K>(d, s, red, 0, rec, F & 7)) return;
+  block_finalize_last<N, K>(s, red, 0);
+  if (threadIdx.x == 0) scalar_step<F>(V, s.res);
+}
+
 // ---------------------------------------------------------------------------
 // Phase bodies.  Each works on the rows [R.lo, R.hi) of one system (R.lo a
 // multiple of 64) and publishes its dot partials as record `rec` of that
@@ -191,7 +240,7 @@ __device__ __forceinline__ void std_init_body(const Csr& A, const Vecs& V, const
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0, rec);
+  publish_step<N, 1, FIN_ENTRY>(d, s, V, red, rec);
 }
 
 // A: S12 (iterations after the first) and S1
@@ -244,7 +293,7 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
       d[0].add(r0, si, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0, rec);
+  publish_step<N, 1, FIN_ALPHA>(d, s, V, red, rec);
 }
 
 // C: S4 + S5
@@ -285,7 +334,7 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
       d[1].add(yi, yi, s.sa + SA_D, &s.flag[1]);
     }
   }
-  block_publish<N, 2>(d, s, red, 0, rec);
+  publish_step<N, 2, FIN_OMEGA>(d, s, V, red, rec);
 }
 
 // E: S8 + S9 + S10/S11 partials
@@ -326,7 +375,7 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
       d[1].add(r, r, s.sa + SA_D, &s.flag[1]);                        // S11
     }
   }
-  block_publish<N, 2>(d, s, red, 0, rec);
+  publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
 }
 
 // true residual ||b - A x|| (reported at exit): partial <e, e> (slot 0)
@@ -344,7 +393,7 @@ __device__ __forceinline__ void resid_body(const Csr& A, const Vecs& V, const Re
       d[0].add(e, e, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0, rec);
+  publish_step<N, 1, FIN_RESID>(d, s, V, red, rec);
 }
 
 // set-up 1 of the pipelined loop: r = b - A x0, r0 = r, r^ = M^-1 r ; partial <r0, r> (slot 0)
@@ -365,7 +414,7 @@ __device__ __forceinline__ void pipe_init1_body(const Csr& A, const Vecs& V, con
       d[0].add(ri, ri, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 0, rec);
+  publish_step<N, 1, FIN_PENTRY1>(d, s, V, red, rec);
 }
 
 // set-up 2: w = A r^, w^ = M^-1 w ; partial <r0, w> (slot 1)
@@ -384,7 +433,7 @@ __device__ __forceinline__ void pipe_init2_body(const Csr& A, const Vecs& V, con
       d[0].add(V.r0[i], wi, s.sa, &s.flag[0]);
     }
   }
-  block_publish<N, 1>(d, s, red, 1, rec);
+  publish_step<N, 1, FIN_PENTRY2>(d, s, V, red, rec);
 }
 
 // out = A in on rows R (the SpMVs of the pipelined loop)
@@ -427,7 +476,7 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
   }
-  block_publish<N, 2>(d, s, red, 0, rec);
+  publish_step<N, 2, FIN_POMEGA>(d, s, V, red, rec);
 }
 
 // P3: S12..S15, S17 and the partials of S16 + <r,r> (slots 0..4)
@@ -458,52 +507,7 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
     d[3].add(r0, V.z[i], s.sa + 3 * SA_D, &s.flag[3]);
     d[4].add(r, r, s.sa + 4 * SA_D, &s.flag[4]);
   }
-  block_publish<N, 5>(d, s, red, 0, rec);
-}
-
-// One finishing workgroup: round the K published dot products of one system
-// and take its scalar step.
-enum : int {
-  FIN_ENTRY = 0,     // <r0,r0>            -> tau0, loop entry test (standard)
-  FIN_ALPHA = 1,     // <r0,s>             -> alpha (S3)
-  FIN_OMEGA = 2,     // <q,y>, <y,y>       -> omega (S7)
-  FIN_BETA = 3,      // <r0,r>, <r,r>      -> tau, stop test, beta (S10, S11)
-  FIN_RESID = 4,     // <e,e>              -> true residual
-  FIN_PENTRY = 5,    // <r0,r0>, <r0,w>    -> tau0, alpha0 (pipelined set-up)
-  FIN_POMEGA = 6,    // <q,y>, <y,y>       -> omega (S11 of the pipelined loop)
-  FIN_S19 = 7        // 5 dots             -> S19
-};
-
-template <int N, int K, int F>
-__device__ __forceinline__ void finish_body(const Vecs& V, const Red& red, const Shm<N>& s) {
-  State* st = V.st;
-  FinPre<N, K> pre;
-  fin_prefetch(pre, red, 0);  // record loads in flight before anything waits
-  State S;
-  state_load(S, st);
-  if (F != FIN_ENTRY && F != FIN_RESID && F != FIN_PENTRY && S.done) return;
-  shm_init(s, K);
-  block_finalize<N, K>(s, red, 0, &pre);
-  if (threadIdx.x != 0) return;
-  if constexpr (F == FIN_ENTRY) {
-    step_entry(&S, s.res[0]);
-    step_loop_entry(&S);
-  } else if constexpr (F == FIN_ALPHA) {
-    step_std_alpha(&S, hist_row(V, S.iter), s.res[0]);
-  } else if constexpr (F == FIN_OMEGA) {
-    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 2);
-  } else if constexpr (F == FIN_BETA) {
-    step_std_beta(&S, hist_row(V, S.iter), s.res[0], s.res[1]);
-  } else if constexpr (F == FIN_RESID) {
-    S.true_res = sqrt(s.res[0]);
-  } else if constexpr (F == FIN_PENTRY) {
-    step_pipe_entry(&S, s.res[0], s.res[1]);
-  } else if constexpr (F == FIN_POMEGA) {
-    step_omega(&S, hist_row(V, S.iter), s.res[0], s.res[1], 0);
-  } else {
-    step_pipe_s19(&S, hist_row(V, S.iter), s.res);
-  }
-  state_store(st, S);
+  publish_step<N, 5, FIN_S19>(d, s, V, red, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,13 +573,6 @@ __global__ void __launch_bounds__(1024) k_resid(Csr A, Vecs V, Red red) {
   resid_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N, int K, int F>
-__global__ void __launch_bounds__(1024) k_finish(Vecs V, Red red) {
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, K, false);
-  finish_body<N, K, F>(V, red, s);
-}
-
 template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
@@ -592,25 +589,14 @@ __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
   pipe_init2_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-// SpMV kernels of the pipelined loop: the workgroup with logical index 0
-// finishes the pending reduction (F), the others compute out = A in.
-template <int N, int K, int F>
-__device__ __forceinline__ void spmv_or_finish(const Csr& A, const Vecs& V, const double* in, double* out,
-                                               const Shm<N>& s, const Red& red) {
-  const int L = xcd_block(blockIdx.x, gridDim.x);
-  if (L == 0) {
-    finish_body<N, K, F>(V, red, s);
-    return;
-  }
-  spmv_body<N>(A, in, out, block_rows(A.n, L - 1, gridDim.x - 1), s);
-}
-
-// set-up 3: t = A w^ || alpha0 = <r0,r0> / <r0,w>
-template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_init3(Csr A, Vecs V, Red red) {
+// The SpMVs of the pipelined loop: W = 0: t = A w^ (set-up 3 and S18), 1: v = A z^ (S10).
+template <int N, int W>
+__global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
+  if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, true);
-  spmv_or_finish<N, 2, FIN_PENTRY>(A, V, V.wh, V.t, s, red);
+  Shm<N> s = shm_carve<N>(smem, 0, true);
+  if (W == 0) spmv_body<N>(A, V.wh, V.t, my_rows(A.n), s);
+  else spmv_body<N>(A, V.zh, V.v, my_rows(A.n), s);
 }
 
 template <int N>
@@ -622,15 +608,6 @@ __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   pipe_P1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-// P2: S10 v = A z^ || S11 omega
-template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_P2(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, true);
-  spmv_or_finish<N, 2, FIN_POMEGA>(A, V, V.zh, V.v, s, red);
-}
-
 template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
@@ -638,15 +615,6 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   Shm<N> s = shm_carve<N>(smem, 5, false);
   shm_init(s, 5);
   pipe_P3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
-}
-
-// P4: S18 t = A w^ || S19
-template <int N>
-__global__ void __launch_bounds__(1024) k_pipe_P4(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 5, true);
-  spmv_or_finish<N, 5, FIN_S19>(A, V, V.wh, V.t, s, red);
 }
 
 }  // namespace rpk
