@@ -81,6 +81,8 @@ typedef struct {
   int32_t variant;     /* rpk_variant                                        */
   int32_t dots;        /* rpk_dotmode                                        */
   int32_t timing;      /* 1: time every kernel with HIP events (no graph)    */
+  int32_t resume;      /* solve: 1 = continue the solve whose state is in the
+                          workspace (see rpk_solve); batched, server: 0     */
   rpk_launch launch;
   double* hist;        /* device, maxit*RPK_HIST_W doubles, or NULL          */
   double* xr_hist;     /* device, maxit*2*n doubles: x then r after each
@@ -150,7 +152,15 @@ rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* opts, 
  * preconditioned, from the initial guess in x; x receives the last full iterate.
  * b, x: n device doubles.  Returns info->status (RPK_OK on convergence); on
  * RPK_NOT_CONVERGED / RPK_BREAKDOWN / RPK_ERR_NONFINITE x holds the last full
- * iterate.  Blocks until the solve is finished. */
+ * iterate.  Blocks until the solve is finished.
+ * Checkpoint / resume: the whole Krylov state (vectors, scalars, counters) lives
+ * in `ws` and x, and ws holds no addresses, so copying ws and x (anywhere, e.g.
+ * to host memory) is a checkpoint.  With opts->resume = 1, rpk_solve continues a
+ * solve that stopped with RPK_NOT_CONVERGED at its iteration limit, from such a
+ * workspace and x (same matrix, b, variant, dots and launch shape), up to
+ * opts->maxit iterations in total; every iterate, scalar (hist rows from the
+ * resumed iteration on) and result is bit-identical to the uninterrupted solve.
+ * A workspace whose solve stopped for another reason returns that status. */
 rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_opts* opts, void* ws,
                      size_t ws_bytes, void* stream, rpk_info* info);
 

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, 
       st->alpha = 0.0; st->omega = 0.0; st->beta = 0.0; st->rho = 0.0;
       st->tau = 0.0; st->tau0 = 0.0; st->tol = tol; st->true_res = 0.0;
       st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
-      st->variant = variant; st->pad0 = 0; st->pad1 = 0; st->pad2 = 0;
+      st->variant = variant; st->resumable = 0; st->pad1 = 0; st->pad2 = 0;
     }
   }
 }

@@ -163,7 +163,7 @@ rpk_status check_opts(const rpk_opts* o) {
   if (!o) return RPK_ERR_ARG;
   if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
   if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
-  if (o->maxit < 0 || !(o->tol >= 0.0) || o->xr_hist) return RPK_ERR_ARG;
+  if (o->maxit < 0 || !(o->tol >= 0.0) || o->xr_hist || o->resume) return RPK_ERR_ARG;
   const rpk_launch& l = o->launch;
   if (l.block && (l.block < 64 || l.block > 1024 || l.block % 64)) return RPK_ERR_ARG;
   if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;

@@ -44,10 +44,12 @@ struct Csr {
 };
 
 // Device-resident solver state (one per solve, in the caller's workspace).
+// resumable: 1 = stopped at maxit with the next iteration's scalars in place,
+// 2 = stopped at maxit where the next step breaks down, 0 = otherwise.
 struct State {
   double alpha, omega, beta, rho, tau, tau0, tol, true_res;
   int iter, maxit, done, status;
-  int variant, pad0, pad1, pad2;
+  int variant, resumable, pad1, pad2;
 };
 
 // Reduction scratch in the caller's workspace (left zeroed after every use).

@@ -402,25 +402,27 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
 
-  // reduction scratch to zero; caller-visible histories to zero
-  hipLaunchKernelGGL(k_zero_words, dim3(16), dim3(256), 0, s, (unsigned*)(w + l.tickets),
+  const bool resume = o->resume != 0;
+  // reduction scratch to zero; caller-visible histories to zero (not when resuming)
+  if (!resume) hipLaunchKernelGGL(k_zero_words, dim3(16), dim3(256), 0, s, (unsigned*)(w + l.tickets),
                      (long long)((l.partials - l.tickets) / sizeof(unsigned)));
   HIPCHK(hipGetLastError());
-  if (o->hist) {
+  if (o->hist && !resume) {
     hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, s, o->hist, (long long)o->maxit * HIST_W, 0.0);
     HIPCHK(hipGetLastError());
   }
-  if (o->xr_hist) {
+  if (o->xr_hist && !resume) {
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, o->xr_hist, (long long)o->maxit * 2 * A->n, 0.0);
     HIPCHK(hipGetLastError());
   }
-  if (variant == RPK_PIPELINED) {  // vectors of iteration -1 start at zero
+  if (variant == RPK_PIPELINED && !resume) {  // vectors of iteration -1 start at zero
     const size_t step = up((size_t)A->n * sizeof(double));
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, (double*)(w + l.vecs),
                        (long long)(16 * step / sizeof(double)), 0.0);
     HIPCHK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_state_setup, dim3(1), dim3(64), 0, s, V.st, o->tol, o->maxit, variant);
+  if (resume) hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, V.st, o->maxit);
+  else hipLaunchKernelGGL(k_state_setup, dim3(1), dim3(64), 0, s, V.st, o->tol, o->maxit, variant);
   HIPCHK(hipGetLastError());
 
   hipEvent_t ev[RPK_NPHASE + 1] = {};
@@ -436,7 +438,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   rpk_status st = RPK_OK;
   do {
     if (timing && hipEventRecord(ev[0], s) != hipSuccess) { st = RPK_ERR_HIP; break; }
-    st = by_fpe<InitF>(N, variant, G, B, s, Ac, V, red);
+    if (!resume) st = by_fpe<InitF>(N, variant, G, B, s, Ac, V, red);
     if (st != RPK_OK) break;
     if (timing) {
       if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }

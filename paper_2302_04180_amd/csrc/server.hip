@@ -371,7 +371,7 @@ rpk_status rpk_server_create(const rpk_server_opts* o, rpk_server** out) {
   if (o->hbm_budget < 4096 || o->max_slots < 1 || o->max_slots > 65536 || o->chunk < 0) return RPK_ERR_ARG;
   if (so.variant != RPK_STD && so.variant != RPK_PIPELINED) return RPK_ERR_ARG;
   if (so.dots != RPK_DOT_EXACT && so.dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
-  if (so.maxit < 0 || !(so.tol >= 0.0) || so.hist || so.xr_hist || so.timing) return RPK_ERR_ARG;
+  if (so.maxit < 0 || !(so.tol >= 0.0) || so.hist || so.xr_hist || so.timing || so.resume) return RPK_ERR_ARG;
   const rpk_launch& l = so.launch;
   if (l.block && (l.block < 64 || l.block > 1024 || l.block % 64)) return RPK_ERR_ARG;
   if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;

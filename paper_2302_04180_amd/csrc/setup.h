@@ -125,4 +125,22 @@ __global__ void k_state_setup(State* st, double tol, int maxit, int variant) {
   }
 }
 
+// Resume a solve stopped at its iteration limit (device state from the same
+// workspace): continue up to `maxit` iterations in total.  A solve that stopped
+// for any other reason keeps its status; one whose next step breaks down now
+// reports the breakdown, as the uninterrupted solve would have.
+__global__ void k_resume(State* st, int maxit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (!st->done || st->status != ST_NOT_CONVERGED || maxit <= st->iter) return;
+  if (st->resumable == 1) {
+    st->done = 0;
+    st->status = 0;
+    st->maxit = maxit;
+    st->resumable = 0;
+  } else if (st->resumable == 2) {
+    st->status = ST_BREAKDOWN;
+    st->resumable = 0;
+  }
+}
+
 }  // namespace rpk

@@ -58,13 +58,14 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.alpha = s->alpha; d.omega = s->omega; d.beta = s->beta; d.rho = s->rho;
   d.tau = s->tau; d.tau0 = s->tau0; d.tol = s->tol; d.true_res = s->true_res;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
-  d.variant = s->variant; d.pad0 = 0; d.pad1 = 0; d.pad2 = 0;
+  d.variant = s->variant; d.resumable = s->resumable; d.pad1 = 0; d.pad2 = 0;
 }
 
 __device__ __forceinline__ void state_store(State* d, const State& s) {
   d->alpha = s.alpha; d->omega = s.omega; d->beta = s.beta; d->rho = s.rho;
   d->tau = s.tau; d->tau0 = s.tau0; d->tol = s.tol; d->true_res = s.true_res;
   d->iter = s.iter; d->maxit = s.maxit; d->done = s.done; d->status = s.status;
+  d->resumable = s.resumable;
 }
 
 __device__ __forceinline__ void stop(State* st, int status) {
@@ -87,8 +88,20 @@ __device__ __forceinline__ void step_entry(State* st, double rho) {
 
 __device__ __forceinline__ void step_loop_entry(State* st) {
   if (st->done) return;
-  if (st->tau / st->tau0 <= st->tol) stop(st, ST_OK);
-  else if (st->maxit <= 0) stop(st, ST_NOT_CONVERGED);
+  if (st->tau / st->tau0 <= st->tol) {
+    stop(st, ST_OK);
+  } else if (st->maxit <= 0) {
+    st->resumable = 1;
+    stop(st, ST_NOT_CONVERGED);
+  }
+}
+
+// Stop at maxit.  The scalars of the next iteration have been computed (not
+// recorded) so that a resumed solve continues exactly where this one stopped;
+// `breaks` marks a next step that would break down.
+__device__ __forceinline__ void stop_at_maxit(State* st, bool breaks) {
+  st->resumable = breaks ? 2 : 1;
+  stop(st, ST_NOT_CONVERGED);
 }
 
 // S3: alpha = rho / <r0, s>
@@ -122,11 +135,12 @@ __device__ __forceinline__ void step_std_beta(State* st, double* h, double rho_n
   st->tau = sqrt(gamma);
   if (h) h[7] = st->tau;
   if (st->tau / st->tau0 <= st->tol) return stop(st, ST_OK);
-  if (st->iter >= st->maxit) return stop(st, ST_NOT_CONVERGED);
-  if (st->rho == 0.0 || st->omega == 0.0) return stop(st, ST_BREAKDOWN);
+  const bool at_max = st->iter >= st->maxit;
+  if (st->rho == 0.0 || st->omega == 0.0) return at_max ? stop_at_maxit(st, true) : stop(st, ST_BREAKDOWN);
   st->beta = (rho_new / st->rho) * (st->alpha / st->omega);
-  if (h) h[8] = st->beta;
+  if (h && !at_max) h[8] = st->beta;
   st->rho = rho_new;
+  if (at_max) stop_at_maxit(st, false);
 }
 
 // pipelined set-up: alpha0 = rho / <r0, w> (after step_entry)
@@ -151,19 +165,20 @@ __device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double
   st->tau = sqrt(gamma);
   if (h) h[8] = st->tau;
   if (st->tau / st->tau0 <= st->tol) return stop(st, ST_OK);
-  if (st->iter >= st->maxit) return stop(st, ST_NOT_CONVERGED);
-  if (st->rho == 0.0 || st->omega == 0.0) return stop(st, ST_BREAKDOWN);
+  const bool at_max = st->iter >= st->maxit;
+  if (st->rho == 0.0 || st->omega == 0.0) return at_max ? stop_at_maxit(st, true) : stop(st, ST_BREAKDOWN);
   const double beta = (rho_new / st->rho) * (st->alpha / st->omega);
   const double delta = fma(beta, fma(-st->omega, zeta, vs), mu_new);
-  if (h) {
+  if (h && !at_max) {
     h[9] = beta;
     h[10] = delta;
   }
-  if (delta == 0.0) return stop(st, ST_BREAKDOWN);
+  if (delta == 0.0) return at_max ? stop_at_maxit(st, true) : stop(st, ST_BREAKDOWN);
   st->beta = beta;
   st->alpha = rho_new / delta;
-  if (h) h[11] = st->alpha;
+  if (h && !at_max) h[11] = st->alpha;
   st->rho = rho_new;
+  if (at_max) stop_at_maxit(st, false);
 }
 
 // Reduction points: which scalar step the last workgroup takes.
@@ -590,9 +605,11 @@ __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
 }
 
 // The SpMVs of the pipelined loop: W = 0: t = A w^ (set-up 3 and S18), 1: v = A z^ (S10).
+// S18 belongs to the iteration after S19: it still runs after a stop at the
+// iteration limit, so that a resumed solve finds t in place.
 template <int N, int W>
 __global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
-  if (V.st->done) return;
+  if (V.st->done && !(W == 0 && V.st->resumable == 1)) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, true);
   if (W == 0) spmv_body<N>(A, V.wh, V.t, my_rows(A.n), s);

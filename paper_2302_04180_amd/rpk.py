@@ -27,7 +27,7 @@ class Launch(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("dots", ctypes.c_int32), ("timing", ctypes.c_int32), ("launch", Launch),
+                ("dots", ctypes.c_int32), ("timing", ctypes.c_int32), ("resume", ctypes.c_int32), ("launch", Launch),
                 ("hist", ctypes.c_void_p), ("xr_hist", ctypes.c_void_p)]
 
 
@@ -186,6 +186,13 @@ def _copy_device(src_ptr, dst):
         raise RuntimeError("hipMemcpy failed: %d" % code)
 
 
+def solve_workspace_bytes(A, variant=STD, dots=EXACT, block=0, grid=0, fpe=0):
+    o = Opts(0.0, 1, int(variant), int(dots), 0, 0, _launch(block, grid, fpe, 0), None, None)
+    nb = ctypes.c_size_t()
+    _check(load().rpk_solve_workspace_bytes(A.handle, ctypes.byref(o), ctypes.byref(nb)), "workspace")
+    return nb.value
+
+
 def exdot(x, y, dots=EXACT, block=0, grid=0, fpe=0):
     """Correctly rounded <x, y> (exact mode) as a 0-dim device tensor."""
     lib = load()
@@ -212,22 +219,35 @@ def exspmv(A, x, out=None, dots=EXACT, block=0, grid=0, fpe=0):
 
 
 def solve(A, b, x0=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, grid=0, fpe=0,
-          graph=0, record=False, record_xr=False, timing=False):
+          graph=0, record=False, record_xr=False, timing=False, workspace=None, resume=False, hist=None):
     """Solve A x = b.  Returns (x, info) with info a dict; info['hist'] / ['xr'] are
-    device tensors when recording was requested."""
+    device tensors when recording was requested.  `workspace` (a uint8 device
+    tensor of at least solve_workspace_bytes) holds the whole solver state: a
+    copy of it and of x is a checkpoint, and resume=True continues such a solve
+    (x0 = its x) up to maxit iterations in total.  `hist` may pass the history
+    tensor to continue filling."""
     lib = load()
     b = _dev(b)
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else _dev(x0).clone()
     m = max(int(maxit), 1)
-    hist = torch.zeros((m, HIST_W), dtype=torch.float64, device=b.device) if record else None
+    if hist is not None:
+        assert hist.shape[0] >= m and hist.shape[1] == HIST_W
+        record = True
+    elif record:
+        hist = torch.zeros((m, HIST_W), dtype=torch.float64, device=b.device)
     xr = torch.zeros((m, 2, A.n), dtype=torch.float64, device=b.device) if record_xr else None
-    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0,
+    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0, 1 if resume else 0,
              _launch(block, grid, fpe, graph),
              ctypes.c_void_p(hist.data_ptr()) if hist is not None else None,
              ctypes.c_void_p(xr.data_ptr()) if xr is not None else None)
     nb = ctypes.c_size_t()
     _check(lib.rpk_solve_workspace_bytes(A.handle, ctypes.byref(o), ctypes.byref(nb)), "workspace")
-    ws = _workspace(nb.value, ("solve", b.device.index))
+    if workspace is not None:
+        assert workspace.is_cuda and workspace.dtype == torch.uint8 and workspace.numel() >= nb.value
+        ws = workspace
+    else:
+        assert not resume, "resuming needs the workspace of the interrupted solve"
+        ws = _workspace(nb.value, ("solve", b.device.index))
     info = Info()
     code = lib.rpk_solve(A.handle, _ptr(b), _ptr(x), ctypes.byref(o), _ptr(ws), ws.numel(), _stream(),
                          ctypes.byref(info))
@@ -265,7 +285,7 @@ def solve_batched(As, bs, x0s=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT
         xs = [_dev(x).clone() for x in x0s]
     m = max(int(maxit), 1)
     hist = torch.zeros((ns, m, HIST_W), dtype=torch.float64, device=bs[0].device) if record else None
-    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0,
+    o = Opts(float(tol), int(maxit), int(variant), int(dots), 1 if timing else 0, 0,
              _launch(block, grid, fpe, graph, tile),
              ctypes.c_void_p(hist.data_ptr()) if hist is not None else None, None)
     Aa = (ctypes.c_void_p * ns)(*[A.handle.value for A in As])
@@ -294,7 +314,7 @@ class Server:
                  dots=EXACT, block=0, fpe=0, tile=0):
         lib = load()
         torch.cuda.init()
-        o = Opts(float(tol), int(maxit), int(variant), int(dots), 0, _launch(block, 0, fpe, 0, tile), None, None)
+        o = Opts(float(tol), int(maxit), int(variant), int(dots), 0, 0, _launch(block, 0, fpe, 0, tile), None, None)
         self._opts = ServerOpts(int(hbm_budget), int(max_slots), int(chunk), o)
         h = ctypes.c_void_p()
         _check(lib.rpk_server_create(ctypes.byref(self._opts), ctypes.byref(h)), "rpk_server_create")

@@ -201,3 +201,47 @@ def test_plain_twin_converges(variant, vname):
     xg, ig = rpk.solve(M, T(b), tol=1e-8, maxit=500, variant=variant, dots=rpk.PLAIN)
     assert ig["status"] == "OK" and 30 <= ig["iters"] <= 70
     assert np.max(np.abs(H(xg) - xs)) < 1e-5
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_checkpoint_resume_is_identical(orc, variant, vname):
+    """A solve stopped at its iteration limit, checkpointed (workspace and x copied
+    to host memory) and resumed from fresh device buffers, possibly several times,
+    ends bit-identical to the uninterrupted solve (and to the oracle)."""
+    import torch
+    A = inputs.convdiff7(12, (0.8, 0.4, 0.2))
+    M = rpk.Matrix(*A)
+    n = 12 ** 3
+    b = rhs(orc, M, A, inputs.uniform(n, 31))
+    tol, maxit = 1e-12, 400
+    xu, iu = rpk.solve(M, T(b), tol=tol, maxit=maxit, variant=variant, record=True)
+    ro = orc.solve(*A, b, tol=tol, maxit=maxit, variant=variant, record=True)
+    compare(ro, xu, iu)
+    k = iu["iters"]
+    assert iu["status"] == "OK" and k > 12
+    nb = rpk.solve_workspace_bytes(M, variant)
+    hist = torch.zeros((maxit, rpk.HIST_W), dtype=torch.float64, device="cuda")
+    cuts = [k // 3, k // 3 + 1, 2 * k // 3]
+    ws = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    x, info = rpk.solve(M, T(b), tol=tol, maxit=cuts[0], variant=variant, workspace=ws, hist=hist)
+    assert info["status"] == "NOT_CONVERGED" and info["iters"] == cuts[0]
+    for m in cuts[1:] + [maxit]:
+        ck_ws, ck_x = ws.cpu(), x.cpu()          # checkpoint ...
+        del ws, x
+        ws, x = ck_ws.cuda(), ck_x.cuda()        # ... restored into new device buffers
+        x, info = rpk.solve(M, T(b), x0=x, tol=tol, maxit=m, variant=variant, workspace=ws, resume=True,
+                            hist=hist)
+        say(vname, "resumed to", m, info["status"], info["iters"])
+        if m < k:
+            assert info["status"] == "NOT_CONVERGED" and info["iters"] == m
+    assert info["status"] == "OK" and info["iters"] == k
+    assert same(H(x), H(xu)) and same(info["tau"], iu["tau"]) and same(info["true_res"], iu["true_res"])
+    hr, hu = H(hist)[:k], H(iu["hist"])[:k]
+    # the scalars of the step after a stop (beta..., taken but not recorded when stopping) are the only gaps
+    gap = [8] if variant == 0 else [9, 10, 11]
+    for m in cuts:
+        hr[m - 1, gap] = hu[m - 1, gap]
+    assert same(hr, hu), first_diff(hr, hu)
+    # resuming a finished solve changes nothing
+    x2, i2 = rpk.solve(M, T(b), x0=x, tol=tol, maxit=maxit + 10, variant=variant, workspace=ws, resume=True)
+    assert i2["status"] == "OK" and i2["iters"] == k and same(H(x2), H(x))
