@@ -23,8 +23,6 @@ constexpr int MAX_DOTS = 8;  // reduction slots in the workspace
 // accumulator.  Digits that fall below the window (data spread over more than
 // ~350 bits) go to the long accumulator directly, so nothing is ever dropped.
 constexpr int WIN = 12;
-constexpr int REC = 16;                        // int64 words of a window record: [0] base digit, [1..WIN]
-constexpr long long REC_EMPTY = -(1ll << 40);  // record of a workgroup whose sum is zero
 
 enum : int { ST_OK = 0, ST_NONFINITE = 5, ST_NOT_CONVERGED = 6, ST_BREAKDOWN = 7 };
 
@@ -74,9 +72,8 @@ __host__ __device__ inline size_t shm_bytes(int N, int K, bool rows, int block) 
   // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D)
   // use the same space at other times
   const size_t scat = (N > 0) ? nw * scat_rows(block) * WIN * 8 : 0;
-  const size_t wsum = (N > 0) ? 16 * WIN * 8 : 0;
-  const size_t wrec = (N > 0) ? MAX_DOTS * REC * 8 : 0;
-  return sa + scat + wsum + wrec + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
+  const size_t wsum = (N > 0) ? (size_t)16 * WIN * (K > 0 ? K : 1) * 8 : 0;
+  return sa + scat + wsum + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
 }
 
 template <int N>
@@ -84,8 +81,7 @@ struct Shm {
   long long* sa;    // K * SA_D    long accumulators (rare path)
   long long* wsa;   // nw * SA_D   row fallback accumulators (aliases scat)
   long long* scat;  // nw * rows * WIN scatter rows
-  long long* wsum;  // 16 * WIN    per-wave window sums
-  long long* wrec;  // MAX_DOTS * REC  window records of this workgroup
+  long long* wsum;  // 16 * K * WIN  per-wave window sums
   double* pbuf;     // 16          plain per-wave sums
   int* imax;        // 16 * MAX_DOTS per-wave maxima
   double* res;      // MAX_DOTS
@@ -105,9 +101,7 @@ __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
   s.wsa = s.scat;
   off += (N > 0) ? nw * scat_rows(blockDim.x) * WIN * 8 : 0;
   s.wsum = (long long*)(base + off);
-  off += (N > 0) ? 16 * WIN * 8 : 0;
-  s.wrec = (long long*)(base + off);
-  off += (N > 0) ? MAX_DOTS * REC * 8 : 0;
+  off += (N > 0) ? (size_t)16 * WIN * (K > 0 ? K : 1) * 8 : 0;
   s.pbuf = (double*)(base + off);
   off += 16 * 8;
   s.imax = (int*)(base + off);
@@ -369,23 +363,14 @@ __device__ __forceinline__ void row_deposit(long long* row, int d0, double c, lo
   }
 }
 
-// Sum the lanes' FPEs of one dot exactly into rec[0..REC) (global): rec[0] = grid
-// digit of window digit 0, rec[1+k] = raw integer sum of digit k.  Each lane
-// adds its components into a private LDS row of WIN digits; lanes then sum the
-// rows column-wise (4 lanes per column) and the waves' columns are added.
+// Wavefront part of the window reduction of one dot: every lane adds its FPE
+// components into a private LDS row of WIN digits (digit 0 = grid digit d0;
+// lower digits go to the long accumulator `sa`), then the rows are summed
+// column-wise (4 lanes per column, combined with shuffles).  Returns the
+// wavefront's sum of window digit `lane` in lanes 0..WIN-1.
 template <int N>
-__device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, long long* sa, int* flag,
-                                             long long* rec) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double mx = 0.0;
-#pragma unroll
-  for (int k = 0; k < N; ++k) mx = fmax(mx, fabs(f.c[k]));
-  const int D = block_max_int(mx != 0.0 ? top_digit(mx) : -1, s);
-  if (D < 0) {
-    if (threadIdx.x == 0) rec[0] = REC_EMPTY;
-    return;
-  }
-  const int d0 = D - (WIN - 1);
+__device__ __forceinline__ long long wave_window(const Fpe<N>& f, int d0, const Shm<N>& s, long long* sa, int* flag) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rows = scat_rows(blockDim.x), quarter = rows / 4;
   long long* R = s.scat + (size_t)w * rows * WIN;
   const int col = lane % WIN, part = lane / WIN;  // lanes < 4*WIN: column, row quarter
@@ -407,15 +392,7 @@ __device__ __forceinline__ void block_window(const Fpe<N>& f, const Shm<N>& s, l
   }
   colsum += __shfl(colsum, (lane + WIN) & 63, 64) + __shfl(colsum, (lane + 2 * WIN) & 63, 64) +
             __shfl(colsum, (lane + 3 * WIN) & 63, 64);
-  if (lane < WIN) s.wsum[w * WIN + lane] = colsum;
-  __syncthreads();
-  if (threadIdx.x < WIN) {
-    long long tot = 0;
-    for (int i = 0; i < nw; ++i) tot += s.wsum[i * WIN + threadIdx.x];
-    rec[1 + threadIdx.x] = tot;
-  }
-  if (threadIdx.x == 0) rec[0] = d0;
-  __syncthreads();
+  return colsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -445,17 +422,37 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
   const int tid = threadIdx.x;
   unsigned long long sink = 0;
   if constexpr (N > 0) {
+    // the K windows together: one block-wide max for all dots, wavefront-local
+    // scatters, one barrier, then the cross-wave sums feed the atomics directly
+    const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
+    int top[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) block_window(d[j].f, s, s.sa + (size_t)j * SA_D, &s.flag[j], s.wrec + j * REC);
+    for (int j = 0; j < K; ++j) {
+      double mx = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) mx = fmax(mx, fabs(d[j].f.c[k]));
+      top[j] = (mx != 0.0) ? top_digit(mx) : -1;
+    }
+    block_max_k<N, K>(top, s);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (top[j] < 0) continue;  // the workgroup's sum of this dot is zero
+      const long long cs = wave_window(d[j].f, top[j] - (WIN - 1), s, s.sa + (size_t)j * SA_D, &s.flag[j]);
+      if (lane < WIN) s.wsum[(w * K + j) * WIN + lane] = cs;
+    }
     __syncthreads();
-    // window digits: thread t < K * WIN adds digit t % WIN of dot t / WIN
     if (tid < K * WIN) {
       const int j = tid / WIN, k = tid % WIN;
-      const long long base = s.wrec[j * REC];
-      const long long v = s.wrec[j * REC + 1 + k];
-      const long long g = base + k;
-      if (base != REC_EMPTY && v != 0 && g >= 0 && g < SA_D)
-        sink += dev_add(red.gsa + (size_t)(slot0 + j) * SA_D + g, v);
+      int tj = top[0];
+#pragma unroll
+      for (int jj = 1; jj < K; ++jj)
+        if (jj == j) tj = top[jj];
+      if (tj >= 0) {
+        long long v = 0;
+        for (int i = 0; i < nw; ++i) v += s.wsum[(i * K + j) * WIN + k];
+        const int g = tj - (WIN - 1) + k;
+        if (v != 0 && g >= 0 && g < SA_D) sink += dev_add(red.gsa + (size_t)(slot0 + j) * SA_D + g, v);
+      }
     }
     // rare: this workgroup's own long accumulators, and the non-finite flags
     if (tid < 64) {
