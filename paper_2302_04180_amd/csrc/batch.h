@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, 
       State* st = D.V.st;
       st->alpha = 0.0; st->omega = 0.0; st->beta = 0.0; st->rho = 0.0;
       st->tau = 0.0; st->tau0 = 0.0; st->tol = tol; st->true_res = 0.0;
+      st->varsigma = 0.0; st->zeta = 0.0;
       st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
       st->variant = variant; st->resumable = 0; st->pad1 = 0; st->pad2 = 0;
     }
@@ -182,8 +183,8 @@ __global__ void __launch_bounds__(1024) kb_pipe_init2(Batch B) {
 template <int N>
 __global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, false);
-  tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+  Shm<N> s = shm_carve<N>(smem, 4, false);
+  tile_loop<N, 4, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
     pipe_P1_body<N>(D.A, D.V, D.red, R, rec, s);
   });
 }
@@ -191,8 +192,8 @@ __global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
 template <int N>
 __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 5, false);
-  tile_loop<N, 5, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+  Shm<N> s = shm_carve<N>(smem, 3, false);
+  tile_loop<N, 3, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
     pipe_P3_body<N>(D.A, D.V, D.red, R, rec, s);
   });
 }

@@ -46,9 +46,9 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
     }
   }
   switch (ph) {
-    case 0: return launch(k_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+    case 0: return launch(k_pipe_P1<N>, G, B, shm_bytes(N, 4, false, B), s, A, V, red);
     case 1: return launch(k_pipe_spmv<N, 1>, G, B, shm_bytes(N, 0, true, B), s, A, V);
-    case 2: return launch(k_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, A, V, red);
+    case 2: return launch(k_pipe_P3<N>, G, B, shm_bytes(N, 3, false, B), s, A, V, red);
     default: return launch(k_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, A, V);
   }
 }
@@ -88,9 +88,9 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
     }
   }
   switch (ph) {
-    case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+    case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 4, false, B), s, b);
     case 1: return launch(kb_pipe_spmv<N, 1>, G, B, shm_bytes(N, 0, true, B), s, b);
-    case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 5, false, B), s, b);
+    case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 3, false, B), s, b);
     default: return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
   }
 }

@@ -46,6 +46,7 @@ struct Csr {
 // 2 = stopped at maxit where the next step breaks down, 0 = otherwise.
 struct State {
   double alpha, omega, beta, rho, tau, tau0, tol, true_res;
+  double varsigma, zeta;  // pipelined: <r0,s>, <r0,z> of the current iteration (S16, taken in P1)
   int iter, maxit, done, status;
   int variant, resumable, pad1, pad2;
 };

@@ -14,9 +14,11 @@
 // Pipelined loop, four kernels per iteration.  The reductions of Fig. 3 are
 // finished at the end of the kernel that produces their terms, so on one GPU
 // there is no latency left for the SpMVs to hide:
-//   P1: S1..S7 + S9 + S8                          -> last workgroup: omega (S11)
+//   P1: S1..S7 + S9 + S8, and <r0,s>, <r0,z> of S16 -> last workgroup: omega (S11)
 //   P2: S10 SpMV
-//   P3: S12..S15 + S17 + S16 (and <r,r> for tau)  -> last workgroup: S19
+//   P3: S12..S15 + S17 + the rest of S16 (and <r,r> for tau) -> last workgroup: S19
+// s and z do not change between S2/S4 and S16, so their two S16 dots are taken
+// where they are produced (P1 reads r0 once instead of P3 reading s and z).
 //   P4: S18 SpMV
 // Every update is the explicit fma written next to it; scalar steps are single
 // IEEE operations in one thread, in the order of the figures.
@@ -57,6 +59,7 @@ __device__ __forceinline__ void record_xr(const Vecs& V, int iter, int n, int ro
 __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.alpha = s->alpha; d.omega = s->omega; d.beta = s->beta; d.rho = s->rho;
   d.tau = s->tau; d.tau0 = s->tau0; d.tol = s->tol; d.true_res = s->true_res;
+  d.varsigma = s->varsigma; d.zeta = s->zeta;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
   d.variant = s->variant; d.resumable = s->resumable; d.pad1 = 0; d.pad2 = 0;
 }
@@ -64,6 +67,7 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
 __device__ __forceinline__ void state_store(State* d, const State& s) {
   d->alpha = s.alpha; d->omega = s.omega; d->beta = s.beta; d->rho = s.rho;
   d->tau = s.tau; d->tau0 = s.tau0; d->tol = s.tol; d->true_res = s.true_res;
+  d->varsigma = s.varsigma; d->zeta = s.zeta;
   d->iter = s.iter; d->maxit = s.maxit; d->done = s.done; d->status = s.status;
   d->resumable = s.resumable;
 }
@@ -190,8 +194,8 @@ enum : int {
   FIN_RESID = 4,     // <e,e>              -> true residual
   FIN_PENTRY1 = 5,   // <r0,r0>            -> tau0 (pipelined set-up)
   FIN_PENTRY2 = 6,   // <r0,w>             -> alpha0, loop entry test
-  FIN_POMEGA = 7,    // <q,y>, <y,y>       -> omega (S11 of the pipelined loop)
-  FIN_S19 = 8        // 5 dots             -> S19
+  FIN_POMEGA = 7,    // <q,y>, <y,y>, <r0,s>, <r0,z> -> omega (S11); <r0,s>, <r0,z> kept for S19
+  FIN_S19 = 8        // <r0,r>, <r0,w>, <r,r> -> S19
 };
 
 template <int F>
@@ -215,8 +219,11 @@ __device__ __forceinline__ void scalar_step(const Vecs& V, const double* res) {
     step_pipe_alpha0(&S, res[0]);
   } else if constexpr (F == FIN_POMEGA) {
     step_omega(&S, hist_row(V, S.iter), res[0], res[1], 0);
+    S.varsigma = res[2];
+    S.zeta = res[3];
   } else {
-    step_pipe_s19(&S, hist_row(V, S.iter), res);
+    const double d5[5] = {res[0], res[1], S.varsigma, S.zeta, res[2]};
+    step_pipe_s19(&S, hist_row(V, S.iter), d5);
   }
   state_store(V.st, S);
 }
@@ -462,17 +469,17 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
   }
 }
 
-// P1: S1..S7, S9 and the partials of S8 (slots 0, 1)
+// P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
 template <int N>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
   const double alpha = st->alpha, beta = st->beta, omega = st->omega;
-  Dot<N> d[2];
-  d[0].zero();
-  d[1].zero();
+  Dot<N> d[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i];
+    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i], r0 = V.r0[i];
     const double ph = fma(beta, fma(-omega, V.sh[i], V.ph[i]), rh);  // S1
     const double sv = fma(beta, fma(-omega, V.z[i], V.s[i]), w);      // S2
     const double sh = fma(beta, fma(-omega, V.zh[i], V.sh[i]), wh);  // S3
@@ -490,20 +497,22 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
     V.zh[i] = A.dinv[i] * z;                                          // S9
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
+    d[2].add(r0, sv, s.sa + 2 * SA_D, &s.flag[2]);                    // S16: <r0,s>
+    d[3].add(r0, z, s.sa + 3 * SA_D, &s.flag[3]);                     //      <r0,z>
   }
-  publish_step<N, 2, FIN_POMEGA>(d, s, V, red, rec);
+  publish_step<N, 4, FIN_POMEGA>(d, s, V, red, rec);
 }
 
-// P3: S12..S15, S17 and the partials of S16 + <r,r> (slots 0..4)
+// P3: S12..S15, S17 and the partials of <r0,r>, <r0,w> (S16) and <r,r> (slots 0..2)
 template <int N>
 __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
   const double alpha = st->alpha, omega = st->omega;
   const int iter = st->iter;
-  Dot<N> d[5];
+  Dot<N> d[3];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) d[j].zero();
+  for (int j = 0; j < 3; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
     const double qh = V.qh[i], y = V.y[i], r0 = V.r0[i];
     const double x = fma(omega, qh, fma(alpha, V.ph[i], V.x[i]));      // S12
@@ -518,11 +527,9 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
     record_xr(V, iter, A.n, i, x, r);
     d[0].add(r0, r, s.sa, &s.flag[0]);                                 // S16
     d[1].add(r0, w, s.sa + SA_D, &s.flag[1]);
-    d[2].add(r0, V.s[i], s.sa + 2 * SA_D, &s.flag[2]);
-    d[3].add(r0, V.z[i], s.sa + 3 * SA_D, &s.flag[3]);
-    d[4].add(r, r, s.sa + 4 * SA_D, &s.flag[4]);
+    d[2].add(r, r, s.sa + 2 * SA_D, &s.flag[2]);                       // tau
   }
-  publish_step<N, 5, FIN_S19>(d, s, V, red, rec);
+  publish_step<N, 3, FIN_S19>(d, s, V, red, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -620,8 +627,8 @@ template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 2, false);
-  shm_init(s, 2);
+  Shm<N> s = shm_carve<N>(smem, 4, false);
+  shm_init(s, 4);
   pipe_P1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
@@ -629,8 +636,8 @@ template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
-  Shm<N> s = shm_carve<N>(smem, 5, false);
-  shm_init(s, 5);
+  Shm<N> s = shm_carve<N>(smem, 3, false);
+  shm_init(s, 3);
   pipe_P3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
