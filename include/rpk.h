@@ -246,6 +246,14 @@ rpk_status rpk_server_get_stats(const rpk_server* s, rpk_server_stats* out);
 /* Finish every submitted request, stop the worker, free the budget. */
 rpk_status rpk_server_destroy(rpk_server* s);
 
+/* Test hook (host only, no device work): the tile table rpk_solve_batched
+ * builds for systems of n[0..nsys-1] rows and `tile` rows per tile.  tiles
+ * receives 4 int32 per tile (system, first row, end row, index of the tile in
+ * its system; system -1 for padding); tile t runs on XCD t % 8.  *ntiles is the
+ * table length; RPK_ERR_ARG if it exceeds cap. */
+rpk_status rpk_plan_tiles(int32_t nsys, const int64_t* n, int32_t tile, int32_t* tiles, int64_t cap,
+                          int64_t* ntiles);
+
 /* Test hook: q[i] = a[i]/b[i] and s[i] = sqrt(a[i]) with the device operations the
  * solver's scalar steps use (to check them against IEEE-754 on the host). */
 rpk_status rpk_device_divsqrt(int64_t n, const double* a, const double* b, double* q, double* s, void* stream);

@@ -484,6 +484,24 @@ rpk_status prepare(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* o, 
 
 extern "C" {
 
+rpk_status rpk_plan_tiles(int32_t nsys, const int64_t* n, int32_t tile, int32_t* tiles, int64_t cap,
+                          int64_t* ntiles) {
+  if (nsys < 1 || nsys > kMaxSys || !n || !tiles || !ntiles || tile < 64 || tile % 64) return RPK_ERR_ARG;
+  std::vector<int64_t> nv(n, n + nsys);
+  for (int64_t v : nv)
+    if (v < 1 || v >= (1ll << 31)) return RPK_ERR_ARG;
+  const Plan p = make_plan(nv, tile);
+  *ntiles = (int64_t)p.tiles.size();
+  if ((int64_t)p.tiles.size() > cap) return RPK_ERR_ARG;
+  for (size_t t = 0; t < p.tiles.size(); ++t) {
+    tiles[4 * t + 0] = p.tiles[t].sys;
+    tiles[4 * t + 1] = p.tiles[t].lo;
+    tiles[4 * t + 2] = p.tiles[t].hi;
+    tiles[4 * t + 3] = p.tiles[t].rec;
+  }
+  return RPK_OK;
+}
+
 rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* o,
                                              size_t* bytes) {
   if (!bytes) return RPK_ERR_ARG;

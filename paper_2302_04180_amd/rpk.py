@@ -55,7 +55,7 @@ EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_des
            "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_solve_batched_workspace_bytes",
            "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
            "rpk_server_poll", "rpk_server_wait", "rpk_server_get_stats", "rpk_server_destroy",
-           "rpk_device_divsqrt"]
+           "rpk_plan_tiles", "rpk_device_divsqrt"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def load(path=LIB_PATH):
     lib.rpk_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Info)]
     lib.rpk_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     lib.rpk_server_destroy.argtypes = [P]
+    lib.rpk_plan_tiles.argtypes = [I32, P, I32, P, I64, ctypes.POINTER(I64)]
     lib.rpk_device_divsqrt.argtypes = [I64, P, P, P, P, P]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = I32
@@ -372,6 +373,18 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def plan_tiles(sizes, tile):
+    """Host-only: the batched solver's tile table for systems of these sizes, as an
+    int32 array of rows (system, first row, end row, tile index in its system)."""
+    n = np.ascontiguousarray(sizes, dtype=np.int64)
+    cap = 8 * (int(np.sum(-(-n // tile))) // 8 + int(np.max(-(-n // tile))) + 2)
+    out = np.zeros((cap, 4), dtype=np.int32)
+    nt = ctypes.c_int64()
+    _check(load().rpk_plan_tiles(n.size, n.ctypes.data, int(tile), out.ctypes.data, cap, ctypes.byref(nt)),
+           "rpk_plan_tiles")
+    return out[:nt.value].copy()
 
 
 def device_divsqrt(a, b):
