@@ -123,6 +123,9 @@ def batched_leg(torch, rpk, inputs, reps=3):
         bs.append(rpk.exspmv(M, torch.tensor(xs, dtype=torch.float64, device="cuda")))
     rows = sum(M.n for M in Ms)
     nnz = sum(M.nnz for M in Ms)
+
+    def std_bytes(M):  # reference bytes of one standard iteration of this system
+        return 2 * (12 * M.nnz + 4 * (M.n + 1)) + 25 * 8 * M.n
     xs, infos = rpk.solve_batched(Ms, bs, tol=1e-8, maxit=500)  # autotuner + graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -143,13 +146,46 @@ def batched_leg(torch, rpk, inputs, reps=3):
     torch.cuda.synchronize()
     t_alone = time.perf_counter() - t1
     ok = all(i["status"] == "OK" for i in infos)
+    alg_bytes = sum(i["iters"] * std_bytes(M) for i, M in zip(infos, Ms))
     for M in Ms:
         M.close()
     return {"systems": len(infos), "rows": rows, "nnz": nnz, "all_converged": ok,
             "solves_per_s": round(len(infos) / dt, 1), "ms_per_batch": round(1e3 * dt, 2),
             "iters_min_max": [min(iters), max(iters)], "iters_total": int(sum(iters)),
             "alone_solves_per_s": round(len(infos) / t_alone, 1),
+            "algorithmic_GBps": round(alg_bytes / dt / 1e9, 1),
+            "roofline_frac": round(alg_bytes / dt / 1e9 / HBM_PEAK_GBS, 4),
             "sampled_results_equal_alone": same, "launch": infos[0]["used"]}
+
+
+def etype_leg(torch, rpk, inputs, reps=2):
+    """The paper's scalability workload on one GPU: nonsymmetric 27-point 'e-type'
+    Poisson 159^3 (n = 4,019,679), b = A*1, x0 = 0, tol 1e-6 (the paper's
+    tolerance), exact and plain, standard and pipelined."""
+    A = inputs.poisson27_etype(159)
+    M = rpk.Matrix(*A)
+    n, nnz = M.n, M.nnz
+    del A
+    b = rpk.exspmv(M, torch.ones(n, dtype=torch.float64, device="cuda"))
+    csr = 12 * nnz + 4 * (n + 1)
+    out = {"n": n, "nnz": nnz, "tol": 1e-6}
+    for variant, vname, vbytes in ((rpk.STD, "std", 25), (rpk.PIPELINED, "pipelined", 42)):
+        for dots, dname in ((rpk.EXACT, "exact"), (rpk.PLAIN, "plain")):
+            rpk.solve(M, b, tol=1e-6, maxit=5000, variant=variant, dots=dots)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it = 0
+            for _ in range(reps):
+                x, info = rpk.solve(M, b, tol=1e-6, maxit=5000, variant=variant, dots=dots)
+                it += info["iters"]
+            torch.cuda.synchronize()
+            ips = it / (time.perf_counter() - t0)
+            gbs = ips * (2 * csr + vbytes * 8 * n) / 1e9
+            out["%s_%s" % (vname, dname)] = {"iters_per_s": round(ips, 1), "iterations": info["iters"],
+                                             "status": info["status"], "algorithmic_GBps": round(gbs, 1),
+                                             "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    M.close()
+    return out
 
 
 def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, seed=2024):
@@ -195,6 +231,7 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
     t_start = time.perf_counter()
     r = 0
     lat, qms, done_t = [], [], []
+    served_bytes = [0]
     check = None
     while r < warm + n_req or out:
         now = time.perf_counter() - t_start
@@ -208,6 +245,7 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
                 continue
             rid, M, b, x = out.pop(t)
             if rid >= warm:
+                served_bytes[0] += res["iters"] * (2 * (12 * M.nnz + 4 * (M.n + 1)) + 42 * 8 * M.n)
                 lat.append(res["latency_ms"])
                 qms.append(res["queue_ms"])
                 done_t.append(time.perf_counter() - t_start)
@@ -227,6 +265,7 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
     lat = np.array(lat)
     return {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
             "offered_solves_per_s": round(lam, 1), "solves_per_s": round(n_req / span, 1),
+            "algorithmic_GBps": round(served_bytes[0] / span / 1e9, 1),
             "latency_ms_p50": round(float(np.percentile(lat, 50)), 2),
             "latency_ms_p99": round(float(np.percentile(lat, 99)), 2),
             "queue_ms_p50": round(float(np.percentile(qms, 50)), 2),
@@ -243,7 +282,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile", action="store_true", help="run the fixed counter-collection workload only")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched, serving and e-type legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -345,6 +384,8 @@ def main():
         result["batched"] = batched_leg(torch, rpk, inputs)
         log("serving leg ...")
         result["serving"] = serving_leg(torch, rpk, inputs)
+        log("27-point e-type leg ...")
+        result["etype27_159"] = etype_leg(torch, rpk, inputs)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(A, args.cpu_iters)

@@ -22,7 +22,7 @@ import hashlib
 
 import numpy as np
 
-__all__ = ["poisson7", "convdiff7", "random_banded", "uniform", "tiny_nonsym",
+__all__ = ["poisson7", "convdiff7", "poisson27_etype", "random_banded", "uniform", "tiny_nonsym",
            "diagonal_pow2", "batched_systems", "sha256", "csr_nnz_poisson7"]
 
 
@@ -62,6 +62,45 @@ def convdiff7(N, P=(0.5, 0.25, 0.125)):
     c = 6.0 + 2.0 * (Px + Py + Pz)
     return _stencil7(N, dict(zm=-(1.0 + 2.0 * Pz), ym=-(1.0 + 2.0 * Py), xm=-(1.0 + 2.0 * Px),
                              c=c, xp=-1.0, yp=-1.0, zp=-1.0))
+
+
+def poisson27_etype(N):
+    """Nonsymmetric 27-point 3D Poisson ('e-type') on an N^3 grid, Dirichlet,
+    natural ordering: diagonal 26, every neighbour -1, except that the entries
+    below the diagonal (column < row) are -(1.0 - 0.0001) (the perturbation of
+    the scalability workload of Sec. 5).  N = 159 gives n = 4,019,679."""
+    n = N ** 3
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % N
+    y = (idx // N) % N
+    z = idx // (N * N)
+    lower = -(1.0 - 0.0001)
+    offs, masks, vals = [], [], []
+    for dz in (-1, 0, 1):
+        mz = (z > 0) if dz < 0 else (z < N - 1) if dz > 0 else None
+        for dy in (-1, 0, 1):
+            my = (y > 0) if dy < 0 else (y < N - 1) if dy > 0 else None
+            for dx in (-1, 0, 1):
+                mx = (x > 0) if dx < 0 else (x < N - 1) if dx > 0 else None
+                m = np.ones(n, bool)
+                for part in (mz, my, mx):
+                    if part is not None:
+                        m &= part
+                o = dz * N * N + dy * N + dx
+                offs.append(o)
+                masks.append(m)
+                vals.append(26.0 if o == 0 else (lower if o < 0 else -1.0))
+    cols = np.empty((n, 27), dtype=np.int32)   # ascending per row (offsets ascend)
+    mask = np.empty((n, 27), dtype=bool)
+    for k, (o, m) in enumerate(zip(offs, masks)):
+        cols[:, k] = (idx + o).astype(np.int32)
+        mask[:, k] = m
+    counts = mask.sum(axis=1)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    ci = cols[mask]
+    v = np.broadcast_to(np.array(vals, dtype=np.float64), (n, 27))[mask]
+    return rp.astype(np.int32), np.ascontiguousarray(ci), np.ascontiguousarray(v)
 
 
 def random_banded(n=500_000, k=19, band=5000, seed=3):

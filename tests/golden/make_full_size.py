@@ -5,7 +5,9 @@ compare with bit for bit.
 Workloads: 7-point Poisson 128^3 with b = A*1, tol 1e-10, maxit 5000, standard
 and pipelined; upwind convection-diffusion 96^3 (cell Peclet 0.5, 0.25, 0.125)
 with b = A*1 and the random banded matrix (n = 500,000, 20 entries per row),
-both pipelined, tol 1e-9, maxit 10000.  Stored per case: SHA-256 of the input
+both pipelined, tol 1e-9, maxit 10000; the nonsymmetric 27-point 'e-type'
+Poisson 159^3 (n = 4,019,679) with b = A*1, tol 1e-6, maxit 5000, standard and
+pipelined.  Stored per case: SHA-256 of the input
 arrays, status, iteration count, tau0, tau, true residual, every recorded
 iteration scalar (hex), SHA-256 of the solution's bytes and a few solution
 entries (hex).
@@ -36,6 +38,8 @@ def cases():
         "poisson128_pipelined": (lambda: inputs.poisson7(128), 1, 1e-10, 5000),
         "convdiff96_pipelined": (lambda: inputs.convdiff7(96), 1, 1e-9, 10000),
         "banded500k_pipelined": (lambda: inputs.random_banded(), 1, 1e-9, 10000),
+        "etype159_std": (lambda: inputs.poisson27_etype(159), 0, 1e-6, 5000),
+        "etype159_pipelined": (lambda: inputs.poisson27_etype(159), 1, 1e-6, 5000),
     }
 
 

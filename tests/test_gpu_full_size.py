@@ -22,6 +22,8 @@ MATRICES = {
     "poisson128_pipelined": lambda: inputs.poisson7(128),
     "convdiff96_pipelined": lambda: inputs.convdiff7(96),
     "banded500k_pipelined": lambda: inputs.random_banded(),
+    "etype159_std": lambda: inputs.poisson27_etype(159),
+    "etype159_pipelined": lambda: inputs.poisson27_etype(159),
 }
 
 

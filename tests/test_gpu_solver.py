@@ -245,3 +245,17 @@ def test_checkpoint_resume_is_identical(orc, variant, vname):
     # resuming a finished solve changes nothing
     x2, i2 = rpk.solve(M, T(b), x0=x, tol=tol, maxit=maxit + 10, variant=variant, workspace=ws, resume=True)
     assert i2["status"] == "OK" and i2["iters"] == k and same(H(x2), H(x))
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS)
+def test_etype27_small_every_scalar(orc, variant, vname):
+    """27-point e-type system (wide rows: 27 entries, several 8-entry batches):
+    every recorded scalar, iterate and the result equal the oracle's."""
+    A = inputs.poisson27_etype(9)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, np.ones(9 ** 3))
+    ro = orc.solve(*A, b, tol=1e-10, maxit=300, variant=variant, record=True, record_xr=True)
+    xg, ig = rpk.solve(M, T(b), tol=1e-10, maxit=300, variant=variant, record=True, record_xr=True)
+    compare(ro, xg, ig)
+    k = ro["iters"]
+    assert same(H(ig["xr"])[:k], ro["xr"][:k])

@@ -101,3 +101,23 @@ def test_jacobi_is_ieee_reciprocal(orc):
     rp, ci, v = inputs.convdiff7(5)
     st, d = orc.jacobi(rp, ci, v)
     assert st == 0 and np.all(d == 1.0 / 7.75)
+
+
+def test_etype27_rows_exact(orc):
+    """27-point e-type matrix: A*1 and A*x (small integers) against exact rational
+    row sums; the matrix is nonsymmetric only through the perturbed lower part."""
+    from fractions import Fraction
+    N = 4
+    rp, ci, v = inputs.poisson27_etype(N)
+    n = N ** 3
+    xs = np.random.default_rng(4).integers(-3, 4, n).astype(np.float64)
+    for x in (np.ones(n), xs):
+        got = orc.exspmv(rp, ci, v, x)
+        for i in range(n):
+            exact = sum(Fraction(v[k]) * Fraction(x[ci[k]]) for k in range(rp[i], rp[i + 1]))
+            assert got[i] == float(exact), (i, got[i], float(exact))
+    # interior row: 26 - 13 - 13*RN(0.9999)
+    i = 1 + N + N * N
+    assert rp[i + 1] - rp[i] == 27
+    lower = v[rp[i]:rp[i + 1]][ci[rp[i]:rp[i + 1]] < i]
+    assert len(lower) == 13 and np.all(lower == -(1.0 - 0.0001))
