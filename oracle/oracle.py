@@ -14,7 +14,7 @@ CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"
           "-shared", "-fPIC", "-Wall"]
 
 HIST_W = 12
-STD, PIPELINED = 0, 1
+STD, PIPELINED, PCG = 0, 1, 2
 STATUS = {0: "OK", 1: "ERR_ARG", 4: "ERR_ZERO_DIAG", 5: "ERR_NONFINITE",
           6: "NOT_CONVERGED", 7: "BREAKDOWN"}
 

@@ -192,7 +192,7 @@ void or_exspmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 /* ------------------------------------------------------------------------- */
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_ZERO_DIAG = 4, OR_ERR_NONFINITE = 5,
        OR_NOT_CONVERGED = 6, OR_BREAKDOWN = 7 };
-enum { OR_STD = 0, OR_PIPELINED = 1 };
+enum { OR_STD = 0, OR_PIPELINED = 1, OR_PCG = 2 };
 #define OR_HIST_W 12
 
 typedef struct {
@@ -440,8 +440,90 @@ done:
 }
 
 /*
+ * Preconditioned conjugate gradient, Fig. 1 (steps S1..S10), Jacobi M.  Set-up
+ * (not printed in the figure): r := b - A x0, y := M^-1 r, p := y,
+ * beta := <y,r>, tau0 := RN(sqrt(<r,r>)).  Then, per iteration:
+ *   S1 d := A p            S2 rho := beta / <p,d>
+ *   S3 x := fma(rho, p, x) S4 r := fma(-rho, d, r)    S5 y := RN(dinv * r)
+ *   S6 alpha := beta       S7 beta := <y,r>           S8 tau := RN(sqrt(<r,r>))
+ *   (stop tests)           S9 alpha := beta / alpha   S10 p := fma(alpha, p, y)
+ * <p,d> = 0 or a zero previous beta is a breakdown.
+ * hist row: [<p,d>, rho, beta, gamma = <r,r>, tau, alpha(S9), 0, 0, 0, 0, 0, 0]
+ */
+static int solve_pcg(const or_mat *A, const double *dinv, const double *b, double *x,
+                     double tol, int maxit, double *hist, double *xr_hist,
+                     int *iters_out, double *tau0_out, double *tau_out) {
+  int64_t n = A->n;
+  double *r = malloc(n * 8), *y = malloc(n * 8), *p = malloc(n * 8), *d = malloc(n * 8);
+  int status = OR_OK, j = 0;
+  double tau0, tau, beta;
+
+  spmv(A, x, d);
+  for (int64_t i = 0; i < n; i++) {
+    r[i] = b[i] - d[i];
+    y[i] = dinv[i] * r[i];
+    p[i] = y[i];
+  }
+  beta = or_exdot(n, y, r);
+  {
+    double gamma = or_exdot(n, r, r);
+    if (isnan(beta) || isnan(gamma)) { status = OR_ERR_NONFINITE; tau0 = tau = NAN; goto done; }
+    tau0 = sqrt(gamma);
+  }
+  tau = tau0;
+  if (tau0 == 0.0) goto done;
+  if (tau / tau0 <= tol) goto done;
+  if (maxit <= 0) { status = OR_NOT_CONVERGED; goto done; }
+
+  for (;;) {
+    double *h = hist ? hist + (int64_t)j * OR_HIST_W : NULL;
+    /* S1 */
+    spmv(A, p, d);
+    /* S2 */
+    double pd = or_exdot(n, p, d);
+    if (h) h[0] = pd;
+    if (isnan(pd)) { status = OR_ERR_NONFINITE; break; }
+    if (pd == 0.0) { status = OR_BREAKDOWN; break; }
+    double rho = beta / pd;
+    if (h) h[1] = rho;
+    /* S3, S4, S5 */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+      x[i] = fma(rho, p[i], x[i]);
+      r[i] = fma(-rho, d[i], r[i]);
+      y[i] = dinv[i] * r[i];
+    }
+    /* S6, S7, S8 */
+    double alpha = beta;
+    beta = or_exdot(n, y, r);
+    double gamma = or_exdot(n, r, r);
+    if (h) { h[2] = beta; h[3] = gamma; }
+    record_xr(xr_hist, n, j, x, r);
+    j++;
+    if (isnan(beta) || isnan(gamma)) { status = OR_ERR_NONFINITE; break; }
+    tau = sqrt(gamma);
+    if (h) h[4] = tau;
+    if (tau / tau0 <= tol) break;
+    if (j >= maxit) { status = OR_NOT_CONVERGED; break; }
+    if (alpha == 0.0) { status = OR_BREAKDOWN; break; }
+    /* S9 */
+    alpha = beta / alpha;
+    if (h) h[5] = alpha;
+    /* S10 */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) p[i] = fma(alpha, p[i], y[i]);
+  }
+done:
+  *iters_out = j;
+  *tau0_out = tau0;
+  *tau_out = tau;
+  free(r); free(y); free(p); free(d);
+  return status;
+}
+
+/*
  * or_solve: solves A x = b from the initial guess in x (overwritten by the last
- * full iterate).  variant 0 = Fig. 2, 1 = Fig. 3.  Stops when RN(tau/tau0) <= tol
+ * full iterate).  variant 0 = Fig. 2, 1 = Fig. 3, 2 = Fig. 1 (PCG).  Stops when RN(tau/tau0) <= tol
  * (relative residual, Sec. 5.1), after maxit iterations, on a zero denominator
  * (breakdown) or on a non-finite dot product.  out[0..3] = {tau0, tau, true
  * residual norm, iterations}.  Returns one of the OR_* codes above.
@@ -450,7 +532,7 @@ int or_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
              const double *b, double *x, double tol, int32_t maxit, int32_t variant,
              double *hist, double *xr_hist, double *out) {
   or_mat A = {n, rp, ci, v};
-  if (n < 1 || (variant != OR_STD && variant != OR_PIPELINED)) return OR_ERR_ARG;
+  if (n < 1 || (variant != OR_STD && variant != OR_PIPELINED && variant != OR_PCG)) return OR_ERR_ARG;
   double *dinv = calloc(n, 8);
   int st = setup_matrix(&A, dinv);
   int iters = 0;
@@ -459,8 +541,10 @@ int or_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
   if (st == OR_OK) {
     if (variant == OR_STD)
       st = solve_std(&A, dinv, b, x, tol, maxit, hist, xr_hist, &iters, &tau0, &tau);
-    else
+    else if (variant == OR_PIPELINED)
       st = solve_pipe(&A, dinv, b, x, tol, maxit, hist, xr_hist, &iters, &tau0, &tau);
+    else
+      st = solve_pcg(&A, dinv, b, x, tol, maxit, hist, xr_hist, &iters, &tau0, &tau);
     double *tmp = calloc(n, 8);
     tres = true_residual(&A, b, x, tmp);
     free(tmp);

@@ -19,7 +19,7 @@ import math
 from fractions import Fraction as F
 
 __all__ = ["rn", "exact_dot", "exact_rowsums", "fma", "IEEE", "Exact", "solve",
-           "dense_solve"]
+           "solve_pcg", "dense_solve"]
 
 
 def rn(q):
@@ -159,6 +159,57 @@ def _diag_inv(A, ar):
         assert len(ks) == 1 and v[ks[0]] != 0
         d.append(ar.inv(v[ks[0]]))
     return d
+
+
+def solve_pcg(A, b, x0=None, tol=1e-8, maxit=50, ar=IEEE, trace=None):
+    """Brute-force preconditioned CG (Fig. 1, Jacobi).  Returns (status, iters, x, r);
+    ``trace`` receives per iteration the scalars and copies of x, r, y, p, d."""
+    rp, ci, v = A
+    n = len(rp) - 1
+    dinv = _diag_inv(A, ar)
+    b = ar.vec(b)
+    x = ar.vec(x0 if x0 is not None else [0.0] * n)
+    t = ar.spmv(A, x)
+    r = [ar.sub(b[i], t[i]) for i in range(n)]
+    y = [ar.mul(dinv[i], r[i]) for i in range(n)]
+    p = list(y)
+    beta = ar.dot(y, r)
+    tau0 = ar.sqrt(ar.dot(r, r))
+    if tau0 == 0 or ar.rel_le(tau0, tau0, tol):
+        return "OK", 0, x, r
+    if maxit <= 0:
+        return "NOT_CONVERGED", 0, x, r
+    j = 0
+    while True:
+        rec = {"p": list(p)}
+        d = ar.spmv(A, p)                                        # S1
+        pd = ar.dot(p, d)                                        # S2
+        rec.update(pd=pd, d=list(d))
+        if pd == 0:
+            if trace is not None:
+                trace.append(rec)
+            return "BREAKDOWN", j, x, r
+        rho = ar.div(beta, pd)
+        x = [ar.fma(rho, p[i], x[i]) for i in range(n)]          # S3
+        r = [ar.fma(-rho, d[i], r[i]) for i in range(n)]         # S4
+        y = [ar.mul(dinv[i], r[i]) for i in range(n)]            # S5
+        alpha = beta                                             # S6
+        beta = ar.dot(y, r)                                      # S7
+        gamma = ar.dot(r, r)                                     # S8
+        tau = ar.sqrt(gamma)
+        j += 1
+        rec.update(rho=rho, beta=beta, gamma=gamma, tau=tau, x=list(x), r=list(r), y=list(y))
+        if trace is not None:
+            trace.append(rec)
+        if ar.rel_le(tau, tau0, tol):
+            return "OK", j, x, r
+        if j >= maxit:
+            return "NOT_CONVERGED", j, x, r
+        if alpha == 0:
+            return "BREAKDOWN", j, x, r
+        alpha = ar.div(beta, alpha)                              # S9
+        rec["alpha"] = alpha
+        p = [ar.fma(alpha, p[i], y[i]) for i in range(n)]        # S10
 
 
 def solve(A, b, x0=None, tol=1e-8, maxit=50, variant=0, ar=IEEE, trace=None):
