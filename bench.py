@@ -63,6 +63,8 @@ def algorithmic_bytes(n, nnz):
         # reference count: every operand of Fig. 2 / Fig. 3 read once, every output written once
         "std_iteration": 2 * csr + 25 * V,
         "pipelined_iteration": 2 * csr + 42 * V,
+        # PCG: S1 CSR + p + d ; S3..S5 x p r d dinv -> x r y ; S10 p y -> p
+        "pcg_iteration": csr + 13 * V,
         # kernels of the standard loop (each operand once):
         # A: p s r dinv -> p p^ ; B: CSR + gather p^ + r0 -> s ; C: s r dinv -> q q^
         # D: CSR + gather q^ + q -> y ; E: x p^ q^ y q r0 -> x r
@@ -335,6 +337,8 @@ def main():
         return k / (time.perf_counter() - t), inf
 
     plain_ips, plain_info = rate(rpk.STD, rpk.PLAIN)
+    pcg_ips, pcg_info = rate(rpk.PCG, rpk.EXACT)
+    pcg_plain_ips, pcg_plain_info = rate(rpk.PCG, rpk.PLAIN)
     pipe_ips, pipe_info = rate(rpk.PIPELINED, rpk.EXACT)
     pplain_ips, pplain_info = rate(rpk.PIPELINED, rpk.PLAIN)
     log("plain std %.1f iters/s (%d it); exact pipelined %.1f (%d it); plain pipelined %.1f (%d it)" % (
@@ -376,6 +380,11 @@ def main():
         "pipelined_exact": {"iters_per_s": round(pipe_ips, 2), "iterations": pipe_info["iters"],
                             "GBps": round(pipe_ips * by["pipelined_iteration"] / 1e9, 1)},
         "pipelined_plain": {"iters_per_s": round(pplain_ips, 2), "iterations": pplain_info["iters"]},
+        # preconditioned CG (Fig. 1) on the same system: one SpMV and CSR + 13V per iteration
+        "pcg_exact": {"iters_per_s": round(pcg_ips, 2), "iterations": pcg_info["iters"],
+                      "GBps": round(pcg_ips * by["pcg_iteration"] / 1e9, 1),
+                      "roofline_frac": round(pcg_ips * by["pcg_iteration"] / 1e9 / HBM_PEAK_GBS, 4)},
+        "pcg_plain": {"iters_per_s": round(pcg_plain_ips, 2), "iterations": pcg_plain_info["iters"]},
         "phase_us": phase,
         "roofline": roofline,
     }

@@ -12,7 +12,8 @@
  *     dot products);
  *   - solve: Jacobi-preconditioned BiCGStab (Fig. 2) or its pipelined variant
  *     (Fig. 3), with every axpy-like update an explicit fma (Sec. 3.3, Sec. 4.1),
- *     stopping when ||r_j|| / ||r_0|| <= tol (Sec. 5.1).
+ *     stopping when ||r_j|| / ||r_0|| <= tol (Sec. 5.1); or the preconditioned
+ *     conjugate gradient of Fig. 1 (for symmetric positive definite A).
  * Exactness makes every result independent of the launch shape, of the order of
  * the data and of how many workgroups cooperate: a result is a function of the
  * inputs alone.  A plain FP64 mode (fma rows in CSR order, tree-reduced dots) is
@@ -54,13 +55,14 @@ typedef enum {
   RPK_REJECTED = 9         /* server: the request can never fit the HBM budget  */
 } rpk_status;
 
-typedef enum { RPK_STD = 0, RPK_PIPELINED = 1 } rpk_variant;
+typedef enum { RPK_STD = 0, RPK_PIPELINED = 1, RPK_PCG = 2 } rpk_variant;
 typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1 } rpk_dotmode;
 
 /* Doubles recorded per iteration when rpk_opts.hist is set.
  *   standard : sigma alpha theta phi omega rho' gamma tau beta 0 0 0
  *   pipelined: theta phi omega rho' mu' <r0,s> <r0,z> gamma tau beta delta alpha'
- * (Fig. 2 / Fig. 3 names; a value not computed because the loop stopped is 0.) */
+ *   PCG      : <p,d> rho beta <r,r> tau alpha 0 0 0 0 0 0
+ * (Fig. 2 / Fig. 3 / Fig. 1 names; a value not computed because the loop stopped is 0.) */
 #define RPK_HIST_W 12
 
 /* Launch shape.  Results of the exact mode do not depend on it. */
@@ -148,8 +150,8 @@ rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t d
 /* Workspace size of rpk_solve for this matrix, options (variant, dots, launch). */
 rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* opts, size_t* bytes);
 
-/* Solve A x = b with PBiCGStab (Fig. 2) or p-PBiCGStab (Fig. 3), Jacobi
- * preconditioned, from the initial guess in x; x receives the last full iterate.
+/* Solve A x = b with PBiCGStab (Fig. 2), p-PBiCGStab (Fig. 3) or PCG (Fig. 1,
+ * symmetric positive definite A), Jacobi preconditioned, from the initial guess in x; x receives the last full iterate.
  * b, x: n device doubles.  Returns info->status (RPK_OK on convergence); on
  * RPK_NOT_CONVERGED / RPK_BREAKDOWN / RPK_ERR_NONFINITE x holds the last full
  * iterate.  Blocks until the solve is finished.
@@ -169,7 +171,7 @@ rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* con
                                              size_t* bytes);
 
 /* Solve nsys independent systems A[k] x[k] = b[k] (host arrays of handles and of
- * device pointers) together: every phase of the iteration is one launch over the
+ * device pointers; variants RPK_STD and RPK_PIPELINED) together: every phase of the iteration is one launch over the
  * rows of all systems still running, each system with its own scalars, stop
  * test and status (Fig. 2 / Fig. 3 per system, as rpk_solve).  Each system's
  * iterates, scalars, iteration count and x are bit-identical to rpk_solve of

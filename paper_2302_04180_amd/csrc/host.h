@@ -37,7 +37,7 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n}; }
 
-inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : 16; }
+inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK_PCG ? 4 : 16; }
 
 template <template <int> class F, typename... Args>
 rpk_status by_fpe(int N, Args&&... args) {

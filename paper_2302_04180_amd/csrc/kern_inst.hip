@@ -24,6 +24,7 @@ rpk_status Kern<N>::spmv(int G, int B, hipStream_t s, Csr A, const double* x, do
 template <int N>
 rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
   if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+  if (variant == RPK_PCG) return launch(k_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   return launch(k_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, A, V);
@@ -43,6 +44,13 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
       case 2: return launch(k_std_C<N>, G, B, 0, s, A, V);
       case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
       default: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+    }
+  }
+  if (variant == RPK_PCG) {
+    switch (ph) {
+      case 0: return launch(k_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
+      case 1: return launch(k_pcg_S3<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      default: return launch(k_pcg_S10<N>, G, B, 0, s, A, V);
     }
   }
   switch (ph) {

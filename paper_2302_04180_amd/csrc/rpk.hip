@@ -348,7 +348,7 @@ rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t d
 
 rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* o, size_t* bytes) {
   if (!A || !o || !bytes) return RPK_ERR_ARG;
-  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED && o->variant != RPK_PCG) return RPK_ERR_ARG;
   Cfg c;
   RET_IF(resolve(&o->launch, A->n, &c));
   *bytes = layout(c.grid, A->n, nvec_of(o->variant)).total;
@@ -362,7 +362,11 @@ static Vecs carve_vecs(char* ws, const Layout& l, int64_t n, int variant, double
   const size_t step = up((size_t)n * sizeof(double));
   double* p[16];
   for (int k = 0; k < nvec_of(variant); ++k) p[k] = (double*)(ws + l.vecs + k * step);
-  V.r0 = p[0]; V.r = p[1]; V.p = p[2]; V.ph = p[3]; V.s = p[4]; V.q = p[5]; V.qh = p[6]; V.y = p[7];
+  if (variant == RPK_PCG) {  // r, p, d (in s), y
+    V.r = p[0]; V.p = p[1]; V.s = p[2]; V.y = p[3];
+  } else {
+    V.r0 = p[0]; V.r = p[1]; V.p = p[2]; V.ph = p[3]; V.s = p[4]; V.q = p[5]; V.qh = p[6]; V.y = p[7];
+  }
   if (variant == RPK_PIPELINED) {
     V.rh = p[8]; V.w = p[9]; V.wh = p[10]; V.t = p[11]; V.sh = p[12]; V.z = p[13]; V.zh = p[14]; V.v = p[15];
   }
@@ -378,7 +382,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
                      void* stream, rpk_info* info) {
   if (!A || !b || !x || !o || !ws || !info) return RPK_ERR_ARG;
   std::memset(info, 0, sizeof(*info));
-  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED && o->variant != RPK_PCG) return RPK_ERR_ARG;
   if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
   if (o->maxit < 0 || !(o->tol >= 0.0)) return RPK_ERR_ARG;
   Cfg c;
@@ -397,7 +401,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   const int variant = o->variant;
   const int N = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
   const int G = c.grid, B = c.block;
-  const int nph = (variant == RPK_STD) ? 5 : 4;
+  const int nph = (variant == RPK_STD) ? 5 : (variant == RPK_PCG) ? 3 : 4;
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
@@ -449,6 +453,11 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
     }
     if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    // PCG: a solve stopped at its limit after S9 still owes S10 (p := y + alpha p),
+    // which opens the next iteration; a resumed solve takes it once here.
+    if (resume && variant == RPK_PCG && !g_pinned->done && g_pinned->iter > 0)
+      st = by_fpe<PhaseF>(N, variant, 2, G, B, s, Ac, V, red);
+    if (st != RPK_OK) break;
     const bool use_graph = !timing && c.graph >= 0;
     int chunk = c.graph > 0 ? c.graph : 4;
     long long launched = 0;

@@ -158,6 +158,49 @@ __device__ __forceinline__ void step_pipe_alpha0(State* st, double mu) {
   step_loop_entry(st);
 }
 
+// PCG set-up: beta := <y,r>, tau0 := ||r||, loop entry test
+__device__ __forceinline__ void step_pcg_entry(State* st, double beta, double gamma) {
+  if (isnan(beta) || isnan(gamma)) {
+    st->tau0 = st->tau = qnan();
+    stop(st, ST_NONFINITE);
+    return;
+  }
+  st->beta = beta;
+  st->tau0 = sqrt(gamma);
+  st->tau = st->tau0;
+  if (st->tau0 == 0.0) stop(st, ST_OK);
+  step_loop_entry(st);
+}
+
+// PCG S2: rho := beta / <p,d>
+__device__ __forceinline__ void step_pcg_rho(State* st, double* h, double pd) {
+  if (h) h[0] = pd;
+  if (isnan(pd)) return stop(st, ST_NONFINITE);
+  if (pd == 0.0) return stop(st, ST_BREAKDOWN);
+  st->rho = st->beta / pd;
+  if (h) h[1] = st->rho;
+}
+
+// PCG S6..S9: alpha := beta, beta := <y,r>, tau := ||r||, stop test, alpha := beta / alpha
+__device__ __forceinline__ void step_pcg_beta(State* st, double* h, double beta, double gamma) {
+  const double alpha = st->beta;
+  if (h) {
+    h[2] = beta;
+    h[3] = gamma;
+  }
+  st->iter += 1;
+  st->beta = beta;
+  if (isnan(beta) || isnan(gamma)) return stop(st, ST_NONFINITE);
+  st->tau = sqrt(gamma);
+  if (h) h[4] = st->tau;
+  if (st->tau / st->tau0 <= st->tol) return stop(st, ST_OK);
+  const bool at_max = st->iter >= st->maxit;
+  if (alpha == 0.0) return at_max ? stop_at_maxit(st, true) : stop(st, ST_BREAKDOWN);
+  st->alpha = beta / alpha;
+  if (h && !at_max) h[5] = st->alpha;
+  if (at_max) stop_at_maxit(st, false);
+}
+
 // S19
 __device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double* d) {
   const double rho_new = d[0], mu_new = d[1], vs = d[2], zeta = d[3], gamma = d[4];
@@ -195,7 +238,10 @@ enum : int {
   FIN_PENTRY1 = 5,   // <r0,r0>            -> tau0 (pipelined set-up)
   FIN_PENTRY2 = 6,   // <r0,w>             -> alpha0, loop entry test
   FIN_POMEGA = 7,    // <q,y>, <y,y>, <r0,s>, <r0,z> -> omega (S11); <r0,s>, <r0,z> kept for S19
-  FIN_S19 = 8        // <r0,r>, <r0,w>, <r,r> -> S19
+  FIN_S19 = 8,       // <r0,r>, <r0,w>, <r,r> -> S19
+  FIN_PCG_ENTRY = 9, // <y,r>, <r,r>       -> beta, tau0, loop entry test (PCG set-up)
+  FIN_PCG_RHO = 10,  // <p,d>              -> rho (S2)
+  FIN_PCG_BETA = 11  // <y,r>, <r,r>       -> beta, tau, stop test, alpha (S6..S9)
 };
 
 template <int F>
@@ -221,9 +267,15 @@ __device__ __forceinline__ void scalar_step(const Vecs& V, const double* res) {
     step_omega(&S, hist_row(V, S.iter), res[0], res[1], 0);
     S.varsigma = res[2];
     S.zeta = res[3];
-  } else {
+  } else if constexpr (F == FIN_S19) {
     const double d5[5] = {res[0], res[1], S.varsigma, S.zeta, res[2]};
     step_pipe_s19(&S, hist_row(V, S.iter), d5);
+  } else if constexpr (F == FIN_PCG_ENTRY) {
+    step_pcg_entry(&S, res[0], res[1]);
+  } else if constexpr (F == FIN_PCG_RHO) {
+    step_pcg_rho(&S, hist_row(V, S.iter), res[0]);
+  } else {
+    step_pcg_beta(&S, hist_row(V, S.iter), res[0], res[1]);
   }
   state_store(V.st, S);
 }
@@ -533,6 +585,82 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
 }
 
 // ---------------------------------------------------------------------------
+// Preconditioned CG (Fig. 1): vectors r, p, d (in V.s), y; x, b
+// ---------------------------------------------------------------------------
+// set-up: r = b - A x0, y = M^-1 r, p = y ; partials <y,r>, <r,r>
+template <int N>
+__device__ __forceinline__ void pcg_init_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                              const Shm<N>& s) {
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double t = rows_wave<N>(A, V.x, i, ok, s.wsa);
+    if (ok) {
+      const double ri = V.b[i] - t;
+      const double yi = A.dinv[i] * ri;
+      V.r[i] = ri;
+      V.y[i] = yi;
+      V.p[i] = yi;
+      d[0].add(yi, ri, s.sa, &s.flag[0]);
+      d[1].add(ri, ri, s.sa + SA_D, &s.flag[1]);
+    }
+  }
+  publish_step<N, 2, FIN_PCG_ENTRY>(d, s, V, red, rec);
+}
+
+// S1 d = A p + partial <p,d> (S2)
+template <int N>
+__device__ __forceinline__ void pcg_S1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                            const Shm<N>& s) {
+  Dot<N> d[1];
+  d[0].zero();
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double pi = ok ? V.p[i] : 0.0;
+    const double di = rows_wave<N>(A, V.p, i, ok, s.wsa);
+    if (ok) {
+      V.s[i] = di;
+      d[0].add(pi, di, s.sa, &s.flag[0]);
+    }
+  }
+  publish_step<N, 1, FIN_PCG_RHO>(d, s, V, red, rec);
+}
+
+// S3 x = fma(rho, p, x), S4 r = fma(-rho, d, r), S5 y = M^-1 r ; partials <y,r>, <r,r> (S7, S8)
+template <int N>
+__device__ __forceinline__ void pcg_S3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                            const Shm<N>& s) {
+  const State* st = V.st;
+  const double rho = st->rho;
+  const int iter = st->iter;
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
+    const double x = fma(rho, V.p[i], V.x[i]);    // S3
+    const double r = fma(-rho, V.s[i], V.r[i]);   // S4
+    const double y = A.dinv[i] * r;               // S5
+    V.x[i] = x;
+    V.r[i] = r;
+    V.y[i] = y;
+    record_xr(V, iter, A.n, i, x, r);
+    d[0].add(y, r, s.sa, &s.flag[0]);             // S7
+    d[1].add(r, r, s.sa + SA_D, &s.flag[1]);      // S8
+  }
+  publish_step<N, 2, FIN_PCG_BETA>(d, s, V, red, rec);
+}
+
+// S10 p = fma(alpha, p, y)
+__device__ __forceinline__ void pcg_S10_body(const Vecs& V, Range R) {
+  const double alpha = V.st->alpha;
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) V.p[i] = fma(alpha, V.p[i], V.y[i]);
+}
+
+// ---------------------------------------------------------------------------
 // Single-system kernels: logical workgroup L (XCD-aware) owns the L-th
 // contiguous row range and publishes record blockIdx.x.
 // ---------------------------------------------------------------------------
@@ -639,6 +767,41 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   Shm<N> s = shm_carve<N>(smem, 3, false);
   shm_init(s, 3);
   pipe_P3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pcg_init(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  shm_init(s, 2);
+  pcg_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pcg_S1(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  shm_init(s, 1);
+  pcg_S1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_pcg_S3(Csr A, Vecs V, Red red) {
+  if (V.st->done) return;
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  shm_init(s, 2);
+  pcg_S3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+// S10 opens the next iteration: after a stop at the iteration limit it is left
+// to the resumed solve (it is not idempotent, and the kernels of the iterations
+// still queued behind the stop see the same state).
+template <int N>
+__global__ void __launch_bounds__(1024) k_pcg_S10(Csr A, Vecs V) {
+  if (V.st->done) return;
+  pcg_S10_body(V, my_rows(A.n));
 }
 
 }  // namespace rpk

@@ -13,7 +13,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpk.so")
 
-STD, PIPELINED = 0, 1
+STD, PIPELINED, PCG = 0, 1, 2
 EXACT, PLAIN = 0, 1
 HIST_W = 12
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_ZERO_DIAG",

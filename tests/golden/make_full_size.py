@@ -7,7 +7,8 @@ and pipelined; upwind convection-diffusion 96^3 (cell Peclet 0.5, 0.25, 0.125)
 with b = A*1 and the random banded matrix (n = 500,000, 20 entries per row),
 both pipelined, tol 1e-9, maxit 10000; the nonsymmetric 27-point 'e-type'
 Poisson 159^3 (n = 4,019,679) with b = A*1, tol 1e-6, maxit 5000, standard and
-pipelined.  Stored per case: SHA-256 of the input
+pipelined; the 128^3 Poisson with the preconditioned conjugate gradient of
+Fig. 1 (tol 1e-10).  Stored per case: SHA-256 of the input
 arrays, status, iteration count, tau0, tau, true residual, every recorded
 iteration scalar (hex), SHA-256 of the solution's bytes and a few solution
 entries (hex).
@@ -40,6 +41,7 @@ def cases():
         "banded500k_pipelined": (lambda: inputs.random_banded(), 1, 1e-9, 10000),
         "etype159_std": (lambda: inputs.poisson27_etype(159), 0, 1e-6, 5000),
         "etype159_pipelined": (lambda: inputs.poisson27_etype(159), 1, 1e-6, 5000),
+        "poisson128_pcg": (lambda: inputs.poisson7(128), 2, 1e-10, 5000),
     }
 
 

@@ -24,6 +24,7 @@ MATRICES = {
     "banded500k_pipelined": lambda: inputs.random_banded(),
     "etype159_std": lambda: inputs.poisson27_etype(159),
     "etype159_pipelined": lambda: inputs.poisson27_etype(159),
+    "poisson128_pcg": lambda: inputs.poisson7(128),
 }
 
 
