@@ -341,6 +341,15 @@ def main():
     pcg_plain_ips, pcg_plain_info = rate(rpk.PCG, rpk.PLAIN)
     pipe_ips, pipe_info = rate(rpk.PIPELINED, rpk.EXACT)
     pplain_ips, pplain_info = rate(rpk.PIPELINED, rpk.PLAIN)
+    # lightweight FPE-8 dots (Sec. 3.2): the same bits when nothing is lost
+    light = {}
+    for vname, var, it_bytes, ref_ips in (("std", rpk.STD, "std_iteration", exact_ips),
+                                          ("pipelined", rpk.PIPELINED, "pipelined_iteration", pipe_ips),
+                                          ("pcg", rpk.PCG, "pcg_iteration", pcg_ips)):
+        ips, inf = rate(var, rpk.FPE)
+        light[vname] = {"iters_per_s": round(ips, 2), "iterations": inf["iters"],
+                        "inexact_dots": inf["inexact_dots"], "time_per_iteration_vs_exact": round(ref_ips / ips, 3)}
+    log("lightweight: " + ", ".join("%s %.1f iters/s" % (k, v["iters_per_s"]) for k, v in light.items()))
     log("plain std %.1f iters/s (%d it); exact pipelined %.1f (%d it); plain pipelined %.1f (%d it)" % (
         plain_ips, plain_info["iters"], pipe_ips, pipe_info["iters"], pplain_ips, pplain_info["iters"]))
 
@@ -352,6 +361,9 @@ def main():
     for k, nm in enumerate(names):
         if tinfo["phase_launches"][k]:
             phase[nm] = round(1e3 * tinfo["phase_ms"][k] / tinfo["phase_launches"][k], 2)  # us per launch
+    tlight = solve(dots=rpk.FPE, timing=True)
+    light["phase_us_std"] = {nm: round(1e3 * tlight["phase_ms"][k] / tlight["phase_launches"][k], 2)
+                             for k, nm in enumerate(names) if tlight["phase_launches"][k]}
     by = algorithmic_bytes(n, nnz)
     dom = max(range(5), key=lambda k: tinfo["phase_ms"][k])
     avg_s = tinfo["phase_ms"][dom] / tinfo["phase_launches"][dom] / 1e3
@@ -385,6 +397,7 @@ def main():
                       "GBps": round(pcg_ips * by["pcg_iteration"] / 1e9, 1),
                       "roofline_frac": round(pcg_ips * by["pcg_iteration"] / 1e9 / HBM_PEAK_GBS, 4)},
         "pcg_plain": {"iters_per_s": round(pcg_plain_ips, 2), "iterations": pcg_plain_info["iters"]},
+        "lightweight_fpe8": light,
         "phase_us": phase,
         "roofline": roofline,
     }

@@ -56,7 +56,20 @@ typedef enum {
 } rpk_status;
 
 typedef enum { RPK_STD = 0, RPK_PIPELINED = 1, RPK_PCG = 2 } rpk_variant;
-typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1 } rpk_dotmode;
+/* Dot products of a solve.
+ *   RPK_DOT_EXACT: exdot (Sec. 2, Sec. 3.2): FPE + long accumulator, correctly
+ *     rounded, reproducible for every input.
+ *   RPK_DOT_PLAIN: the non-reproducible FP64 twin (fma partials, tree sums).
+ *   RPK_DOT_FPE:   the lightweight dot of Sec. 3.2: FPEs of 8 doubles with early
+ *     exit and no long accumulator, merged across lanes and workgroups with
+ *     twosum cascades and rounded once.  When no part of a sum is lost its
+ *     result is the correctly rounded dot, bit-identical to RPK_DOT_EXACT;
+ *     otherwise (more than 8 components needed, or a product p with |p| outside
+ *     [2^-968, 2^990)) the lost part is added in plain FP64 and the dot is
+ *     counted in rpk_info.inexact_dots -- the warning that RPK_DOT_EXACT should be
+ *     used for that problem.  Single solves (rpk_solve) and rpk_fpedot only.
+ * The CSR rows of the SpMV are exact in every mode but RPK_DOT_PLAIN. */
+typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1, RPK_DOT_FPE = 2 } rpk_dotmode;
 
 /* Doubles recorded per iteration when rpk_opts.hist is set.
  *   standard : sigma alpha theta phi omega rho' gamma tau beta 0 0 0
@@ -103,6 +116,9 @@ typedef struct {
   rpk_launch used;     /* the launch shape that ran (after defaults / autotuning) */
   double queue_ms;     /* server: submission -> admission (host monotonic clock) */
   double latency_ms;   /* server: submission -> result ready                     */
+  int32_t inexact_dots; /* RPK_DOT_FPE: dot products that could not keep every bit
+                           (0: the solve is bit-identical to RPK_DOT_EXACT)       */
+  int32_t reserved;
 } rpk_info;
 
 typedef struct rpk_matrix rpk_matrix;
@@ -141,8 +157,18 @@ rpk_status rpk_exdot_workspace_bytes(int64_t n, const rpk_launch* launch, size_t
 rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
                      const rpk_launch* launch, void* ws, size_t ws_bytes, void* stream);
 
+/* Lightweight dot (Sec. 3.2, RPK_DOT_FPE): *out_dev = RN of the sum held by the
+ * merged FPE-8s, plus, when something did not fit, the lost part added in plain
+ * FP64; *lost_dev (one device int32) = 0 when every bit was kept -- then
+ * *out_dev equals rpk_exdot bit for bit, for any launch shape -- and 1 otherwise
+ * (the result is accurate but not guaranteed correctly rounded or reproducible:
+ * use rpk_exdot).  Any non-finite factor gives NaN.  Same workspace as
+ * rpk_exdot (rpk_exdot_workspace_bytes), n < 2^32.  Asynchronous on `stream`. */
+rpk_status rpk_fpedot(int64_t n, const double* x, const double* y, double* out_dev, int32_t* lost_dev,
+                      const rpk_launch* launch, void* ws, size_t ws_bytes, void* stream);
+
 /* y = A x with y_i = RN(sum_j a_ij x_j) of the exact row sum (Sec. 4.1 SpMV,
- * exact); plain mode: sequential fma in CSR order.  x, y: n device doubles, must
+ * exact; RPK_DOT_FPE gives the same exact rows); plain mode: sequential fma in CSR order.  x, y: n device doubles, must
  * not overlap.  Asynchronous on `stream`. */
 rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t dots, const rpk_launch* launch,
                       void* stream);
@@ -171,7 +197,7 @@ rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* con
                                              size_t* bytes);
 
 /* Solve nsys independent systems A[k] x[k] = b[k] (host arrays of handles and of
- * device pointers; variants RPK_STD and RPK_PIPELINED) together: every phase of the iteration is one launch over the
+ * device pointers; variants RPK_STD and RPK_PIPELINED, dots RPK_DOT_EXACT or RPK_DOT_PLAIN) together: every phase of the iteration is one launch over the
  * rows of all systems still running, each system with its own scalars, stop
  * test and status (Fig. 2 / Fig. 3 per system, as rpk_solve).  Each system's
  * iterates, scalars, iteration count and x are bit-identical to rpk_solve of

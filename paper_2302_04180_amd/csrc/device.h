@@ -436,7 +436,9 @@ __device__ __forceinline__ int top_digit(double x) {
 // ---------------------------------------------------------------------------
 // Exact accumulation of products into an FPE with long-accumulator fallback
 // ---------------------------------------------------------------------------
-enum : int { F_SA = 1, F_NONFINITE = 2 };
+// F_LOST: lightweight mode only -- a part of the sum did not fit an FPE (or a
+// product was outside the exact twoprod range) and was added in plain FP64.
+enum : int { F_SA = 1, F_NONFINITE = 2, F_LOST = 4 };
 
 // acc += a*b exactly.  Leftovers and extreme products go to the LDS long
 // accumulator `sa`; `flag` collects F_SA / F_NONFINITE.

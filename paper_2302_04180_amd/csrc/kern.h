@@ -1,5 +1,6 @@
 // kern.h -- host launchers of the templated kernels, one explicit
-// instantiation per FPE length (0 = plain FP64) in its own translation unit.
+// instantiation per FPE length (0 = plain FP64, LW8 = lightweight dots) in its
+// own translation unit.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -17,7 +18,7 @@ namespace rpk {
 template <int N>
 struct Kern {
   static rpk_status dot(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* out,
-                        Red red);
+                        int* lost, Red red);
   static rpk_status spmv(int G, int B, hipStream_t s, Csr A, const double* x, double* y);
   static rpk_status init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red);
   static rpk_status resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red);
@@ -40,6 +41,7 @@ extern template struct Kern<1>;
 extern template struct Kern<2>;
 extern template struct Kern<4>;
 extern template struct Kern<8>;
+extern template struct Kern<LW8>;  // lightweight dots: single solves and rpk_fpedot only
 extern template struct KernB<0>;
 extern template struct KernB<1>;
 extern template struct KernB<2>;

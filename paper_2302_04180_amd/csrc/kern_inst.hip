@@ -1,5 +1,6 @@
 // kern_inst.hip -- launchers of Kern<RPK_N>; compiled once per FPE length
-// (RPK_N = 0 plain FP64, 1, 2, 4, 8) so the instantiations build in parallel.
+// (RPK_N = 0 plain FP64, 1, 2, 4, 8 exact, 9 = LW8 lightweight) so the
+// instantiations build in parallel.
 #include "kern.h"
 
 namespace rpk {
@@ -12,8 +13,8 @@ static rpk_status launch(K kernel, int grid, int block, size_t shm, hipStream_t 
 
 template <int N>
 rpk_status Kern<N>::dot(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* out,
-                        Red red) {
-  return launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, out, red);
+                        int* lost, Red red) {
+  return launch(k_dot<N>, G, B, shm_bytes(N, 1, false, B), s, n, x, y, out, lost, red);
 }
 
 template <int N>
@@ -104,6 +105,8 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
 }
 
 template struct Kern<RPK_N>;
+#if RPK_N != 9  // the batched solver and the server run exact or plain dots only
 template struct KernB<RPK_N>;
+#endif
 
 }  // namespace rpk

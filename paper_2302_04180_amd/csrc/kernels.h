@@ -2,7 +2,10 @@
 //
 // N > 0 selects the exact arithmetic (FPE of length N + long accumulator, one
 // rounding per dot product and per CSR row); N == 0 selects the plain FP64
-// comparison path (fma row sums in CSR order, fma dot partials, tree reduction).
+// comparison path (fma row sums in CSR order, fma dot partials, tree reduction);
+// N == LW8 selects the lightweight dot products of Sec. 3.2 (FPEs of length 8
+// with early exit, merged with twosum cascades across lanes and workgroups,
+// rounded once; bits that do not fit are flagged) with the exact CSR rows.
 //
 // Row partitioning: the grid has G workgroups; logical block L owns a contiguous
 // range of rows.  The hardware hands workgroups to the 8 XCDs round-robin, so
@@ -23,6 +26,14 @@ constexpr int MAX_DOTS = 8;  // reduction slots in the workspace
 // accumulator.  Digits that fall below the window (data spread over more than
 // ~350 bits) go to the long accumulator directly, so nothing is ever dropped.
 constexpr int WIN = 12;
+// Lightweight mode: FPE length 8; each workgroup publishes a record of LW_REC
+// doubles per dot (8 components, the plain tail, the flags as a double).
+constexpr int LW8 = 9;
+constexpr int LW_N = 8;
+constexpr int LW_REC = 10;
+// FPE length of the exact row sums (the lightweight mode keeps the exact rows)
+template <int N>
+constexpr int kRowN = (N == LW8) ? 4 : N;
 
 enum : int { ST_OK = 0, ST_NONFINITE = 5, ST_NOT_CONVERGED = 6, ST_BREAKDOWN = 7 };
 
@@ -48,7 +59,9 @@ struct State {
   double alpha, omega, beta, rho, tau, tau0, tol, true_res;
   double varsigma, zeta;  // pipelined: <r0,s>, <r0,z> of the current iteration (S16, taken in P1)
   int iter, maxit, done, status;
-  int variant, resumable, pad1, pad2;
+  int variant, resumable;
+  int lost;  // lightweight mode: dot products that could not keep every bit
+  int pad2;
 };
 
 // Reduction scratch in the caller's workspace (left zeroed after every use).
@@ -69,7 +82,7 @@ __host__ __device__ inline int scat_rows(int block) { return block <= 512 ? 64 :
 __host__ __device__ inline size_t shm_bytes(int N, int K, bool rows, int block) {
   (void)rows;
   const size_t nw = (size_t)block / 64;
-  const size_t sa = (N > 0) ? (size_t)K * SA_D * 8 : 0;
+  const size_t sa = (N > 0 && N != LW8) ? (size_t)K * SA_D * 8 : 0;
   // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D)
   // use the same space at other times
   const size_t scat = (N > 0) ? nw * scat_rows(block) * WIN * 8 : 0;
@@ -82,7 +95,7 @@ struct Shm {
   long long* sa;    // K * SA_D    long accumulators (rare path)
   long long* wsa;   // nw * SA_D   row fallback accumulators (aliases scat)
   long long* scat;  // nw * rows * WIN scatter rows
-  long long* wsum;  // 16 * K * WIN  per-wave window sums
+  long long* wsum;  // 16 * K * WIN  per-wave window sums (lightweight: 16 * K * LW_REC doubles)
   double* pbuf;     // 16          plain per-wave sums
   int* imax;        // 16 * MAX_DOTS per-wave maxima
   double* res;      // MAX_DOTS
@@ -97,7 +110,7 @@ __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
   const size_t nw = blockDim.x / 64;
   size_t off = 0;
   s.sa = (long long*)(base + off);
-  off += (N > 0) ? (size_t)K * SA_D * 8 : 0;
+  off += (N > 0 && N != LW8) ? (size_t)K * SA_D * 8 : 0;
   s.scat = (long long*)(base + off);
   s.wsa = s.scat;
   off += (N > 0) ? nw * scat_rows(blockDim.x) * WIN * 8 : 0;
@@ -118,7 +131,7 @@ __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
 // zero the K long accumulators and flags of this block (must precede any deposit)
 template <int N>
 __device__ __forceinline__ void shm_init(const Shm<N>& s, int K) {
-  if (N > 0)
+  if (N > 0 && N != LW8)
     for (int k = threadIdx.x; k < K * SA_D; k += blockDim.x) s.sa[k] = 0;
   if (threadIdx.x < MAX_DOTS) s.flag[threadIdx.x] = 0;
   __syncthreads();
@@ -164,6 +177,72 @@ struct Dot<0> {
   double s;
   __device__ __forceinline__ void zero() { s = 0.0; }
   __device__ __forceinline__ void add(double a, double b, long long*, int*) { s = fma(a, b, s); }
+};
+
+// Lightweight accumulator (Sec. 3.2): an FPE of 8 doubles with early exit and
+// nothing behind it.  What the FPE cannot hold (a cascade that still carries an
+// error after the last component, or a product outside the range where twoprod
+// is exact) is added to a plain FP64 tail and flagged F_LOST: the result is then
+// accurate but no longer guaranteed to be correctly rounded or reproducible.
+// When nothing is lost, the FPE holds the exact sum and its rounding equals the
+// exact dot product bit for bit.
+template <>
+struct Dot<LW8> {
+  Fpe<LW_N> f;
+  double tail;
+  int fl;
+  __device__ __forceinline__ void zero() {
+    fpe_zero(f);
+    tail = 0.0;
+    fl = 0;
+  }
+  // insert one double (all lanes of the wavefront call it together)
+  __device__ __forceinline__ void put(double x) {
+    const double l = fpe_add_w<LW_N, 0>(f, x);
+    if (l != 0.0) {
+      tail += l;
+      fl |= F_LOST;
+    }
+  }
+  __device__ __forceinline__ void add(double a, double b, long long*, int*) {
+    const double p = a * b;
+    const double ap = fabs(p);
+    const bool ok = ap >= kProdLo && ap < kProdHi;
+    const double e = ok ? fma(a, b, -p) : 0.0;
+    const double l1 = fpe_add_w<LW_N, 0>(f, ok ? p : 0.0);
+    const double l2 = fpe_add_w<LW_N, 1>(f, e);
+    const bool extreme = !ok && !(p == 0.0 && (a == 0.0 || b == 0.0));
+    if (l1 != 0.0 || l2 != 0.0 || extreme) {
+      if (!isfinite(a) || !isfinite(b)) {
+        fl |= F_NONFINITE;
+      } else {
+        tail += l1;
+        tail += l2;
+        if (extreme) tail = fma(a, b, tail);
+        fl |= F_LOST;
+      }
+    }
+  }
+  // absorb another accumulator's record (components largest first)
+  __device__ __forceinline__ void absorb(const double (&c)[LW_N], double t, int f2) {
+#pragma unroll
+    for (int k = 0; k < LW_N; ++k) put(c[k]);
+    tail += t;
+    fl |= f2;
+  }
+  // merge over the lanes of the wavefront whose index differs below `width`
+  // (a power of two <= 64); lane 0 ends with the merged value of lanes 0..width-1
+  __device__ __forceinline__ void wave_merge(int width) {
+#pragma unroll 1
+    for (int off = 1; off < width; off <<= 1) {  // kept rolled: the body is large
+      double c[LW_N];
+#pragma unroll
+      for (int k = 0; k < LW_N; ++k) c[k] = __shfl_xor(f.c[k], off, 64);
+      const double t = __shfl_xor(tail, off, 64);
+      const int f2 = __shfl_xor(fl, off, 64);
+      absorb(c, t, f2);
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -270,7 +349,7 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     return acc;
   } else {
     bool bad = false;
-    double y = row_fast<N>(sv, sc, gx, w, bad);
+    double y = row_fast<kRowN<N>>(sv, sc, gx, w, bad);
     bad = bad && valid;
     unsigned long long m = __ballot(bad);
     if (m) {
@@ -415,6 +494,35 @@ __device__ __forceinline__ unsigned long long dev_add(long long* p, long long v)
                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Lightweight records: 8 components, tail, flags.
+__device__ __forceinline__ void lw_pack(double (&v)[LW_REC], const Dot<LW8>& a) {
+#pragma unroll
+  for (int k = 0; k < LW_N; ++k) v[k] = a.f.c[k];
+  v[LW_N] = a.tail;
+  v[LW_N + 1] = (double)a.fl;
+}
+
+__device__ __forceinline__ void lw_store(double* r, const Dot<LW8>& a) {
+  double v[LW_REC];
+  lw_pack(v, a);
+#pragma unroll
+  for (int k = 0; k < LW_REC; ++k) r[k] = v[k];
+}
+
+// One wavefront merges the per-wave records (wave i at rec[(i*K + j)*LW_REC])
+// of dot j; lane 0 ends with the workgroup's value.
+__device__ __forceinline__ void lw_gather_waves(Dot<LW8>& a, const double* rec, int j, int K, int nw, int lane) {
+  const bool in = lane < nw;
+  const double* r = rec + (size_t)(lane * K + j) * LW_REC;
+#pragma unroll
+  for (int k = 0; k < LW_N; ++k) a.f.c[k] = in ? r[k] : 0.0;
+  a.tail = in ? r[LW_N] : 0.0;
+  a.fl = in ? (int)r[LW_N + 1] : 0;
+  int width = 1;
+  while (width < nw) width <<= 1;
+  a.wave_merge(width);
+}
+
 // Returns true (in every thread) in the last workgroup to arrive.  `ticket`
 // selects the arrival counter (kernels that run one after the other may share).
 template <int N, int K>
@@ -422,7 +530,31 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
                                                    int b, int ticket) {
   const int tid = threadIdx.x;
   unsigned long long sink = 0;
-  if constexpr (N > 0) {
+  if constexpr (N == LW8) {
+    // twosum merge trees: lanes of each wave (shuffles), then the waves (LDS,
+    // one wave per dot); lane 0 publishes the workgroup's record of each dot
+    const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
+    double* rec = (double*)s.wsum;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      d[j].wave_merge(64);
+      if (lane == 0) lw_store(rec + (size_t)(w * K + j) * LW_REC, d[j]);
+    }
+    __syncthreads();
+    for (int j = w; j < K; j += nw) {
+      Dot<LW8> a;
+      lw_gather_waves(a, rec, j, K, nw, lane);
+      if (lane == 0) {
+        double* g = red.partials + ((size_t)(slot0 + j) * red.G + b) * LW_REC;
+        double v[LW_REC];
+        lw_pack(v, a);
+#pragma unroll
+        for (int k = 0; k < LW_REC; ++k)
+          sink += __hip_atomic_exchange((unsigned long long*)&g[k], (unsigned long long)__double_as_longlong(v[k]),
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  } else if constexpr (N > 0) {
     // the K windows together: one block-wide max for all dots, wavefront-local
     // scatters, one barrier, then the cross-wave sums feed the atomics directly
     const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
@@ -501,7 +633,41 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
 template <int N, int K>
 __device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& red, int slot0) {
   const int tid = threadIdx.x, bd = blockDim.x;
-  if constexpr (N > 0) {
+  if constexpr (N == LW8) {
+    const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
+    double* rec = (double*)s.wsum;
+    for (int j = 0; j < K; ++j) {
+      Dot<LW8> a;
+      a.zero();
+      for (int b = tid; b < red.G; b += bd) {
+        const double* g = red.partials + ((size_t)(slot0 + j) * red.G + b) * LW_REC;
+        double v[LW_REC];
+#pragma unroll
+        for (int k = 0; k < LW_REC; ++k)
+          v[k] = __longlong_as_double((long long)__hip_atomic_load((unsigned long long*)&g[k], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT));
+        double c[LW_N];
+#pragma unroll
+        for (int k = 0; k < LW_N; ++k) c[k] = v[k];
+        a.absorb(c, v[LW_N], (int)v[LW_N + 1]);
+      }
+      a.wave_merge(64);
+      if (lane == 0) lw_store(rec + (size_t)(w * K + j) * LW_REC, a);
+    }
+    __syncthreads();
+    for (int j = w; j < K; j += nw) {
+      Dot<LW8> a;
+      lw_gather_waves(a, rec, j, K, nw, lane);
+      if (lane == 0) {
+        double r = fpe_round(a.f);
+        if (a.fl & F_LOST) r += a.tail;
+        if (a.fl & F_NONFINITE) r = __longlong_as_double(0x7ff8000000000000ll);
+        s.res[j] = r;
+        s.misc[1 + j] = a.fl;
+      }
+    }
+    __syncthreads();
+  } else if constexpr (N > 0) {
     for (int i = tid; i < K * SA_D; i += bd) {
       const int j = i / SA_D, k = i - j * SA_D;
       s.sa[i] = (long long)__hip_atomic_exchange((unsigned long long*)&red.gsa[(size_t)(slot0 + j) * SA_D + k], 0ull,
@@ -554,7 +720,7 @@ __device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& 
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(1024) k_dot(long long n, const double* __restrict__ x,
-                                              const double* __restrict__ y, double* out, Red red) {
+                                              const double* __restrict__ y, double* out, int* lost, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, false);
   shm_init(s, 1);
@@ -569,7 +735,10 @@ __global__ void __launch_bounds__(1024) k_dot(long long n, const double* __restr
   for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) d[0].add(x[i], y[i], s.sa, &s.flag[0]);
   if (!block_publish_last<N, 1>(d, s, red, 0, blockIdx.x, 0)) return;
   block_finalize_last<N, 1>(s, red, 0);
-  if (threadIdx.x == 0) out[0] = s.res[0];
+  if (threadIdx.x == 0) {
+    out[0] = s.res[0];
+    if (lost) lost[0] = (N == LW8 && (s.misc[1] & F_LOST)) ? 1 : 0;
+  }
 }
 
 template <int N>

@@ -64,7 +64,7 @@ Layout layout(int grid, int64_t n, int nvec) {
   l.gsa = off;
   off += up((size_t)MAX_DOTS * SA_D * sizeof(long long));
   l.partials = off;
-  off += up((size_t)MAX_DOTS * grid * sizeof(double));  // plain-mode workgroup sums
+  off += up((size_t)MAX_DOTS * grid * LW_REC * sizeof(double));  // plain sums / lightweight records per workgroup
   l.vecs = off;
   off += (size_t)nvec * up((size_t)n * sizeof(double));
   l.total = off;
@@ -84,8 +84,8 @@ Red make_red(char* ws, const Layout& l, int grid) {
 template <int N>
 struct DotF {
   static rpk_status call(int G, int B, hipStream_t s, long long n, const double* x, const double* y, double* o,
-                         Red r) {
-    return Kern<N>::dot(G, B, s, n, x, y, o, r);
+                         int* lost, Red r) {
+    return Kern<N>::dot(G, B, s, n, x, y, o, lost, r);
   }
 };
 template <int N>
@@ -106,6 +106,15 @@ struct PhaseF {
     return Kern<N>::phase(variant, ph, G, B, s, A, V, r);
   }
 };
+
+// the instantiations of a single solve or dot: plain, exact (FPE length N) or lightweight
+template <template <int> class F, typename... Args>
+rpk_status by_dot(int N, Args&&... args) {
+  if (N == LW8) return F<LW8>::call(args...);
+  return by_fpe<F>(N, args...);
+}
+
+int kernel_n(int dots, int fpe) { return dots == RPK_DOT_PLAIN ? 0 : dots == RPK_DOT_FPE ? LW8 : fpe; }
 
 // ---------------------------------------------------------------------------
 // library-wide state
@@ -332,17 +341,28 @@ rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_de
   const Layout l = layout(c.grid, 0, 0);
   if (ws_bytes < l.total) return RPK_ERR_ARG;
   Red red = make_red((char*)ws, l, c.grid);
-  const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
-  return by_fpe<DotF>(N, c.grid, c.block, (hipStream_t)stream, (long long)n, x, y, out_dev, red);
+  const int N = kernel_n(dots, c.fpe);
+  return by_dot<DotF>(N, c.grid, c.block, (hipStream_t)stream, (long long)n, x, y, out_dev, (int*)nullptr, red);
+}
+
+rpk_status rpk_fpedot(int64_t n, const double* x, const double* y, double* out_dev, int32_t* lost_dev,
+                      const rpk_launch* launch_cfg, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= (1ll << 32) || !out_dev || !lost_dev || !ws || (n > 0 && (!x || !y))) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(launch_cfg, n, &c));
+  const Layout l = layout(c.grid, 0, 0);
+  if (ws_bytes < l.total) return RPK_ERR_ARG;
+  Red red = make_red((char*)ws, l, c.grid);
+  return by_dot<DotF>(LW8, c.grid, c.block, (hipStream_t)stream, (long long)n, x, y, out_dev, (int*)lost_dev, red);
 }
 
 rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t dots, const rpk_launch* launch_cfg,
                       void* stream) {
   if (!A || !x || !y || x == y) return RPK_ERR_ARG;
-  if (dots != RPK_DOT_EXACT && dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  if (dots != RPK_DOT_EXACT && dots != RPK_DOT_PLAIN && dots != RPK_DOT_FPE) return RPK_ERR_ARG;
   Cfg c;
   RET_IF(resolve(launch_cfg, A->n, &c));
-  const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;  // the lightweight mode keeps the exact rows
   return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, csr_of(A), x, y);
 }
 
@@ -383,7 +403,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   if (!A || !b || !x || !o || !ws || !info) return RPK_ERR_ARG;
   std::memset(info, 0, sizeof(*info));
   if (o->variant != RPK_STD && o->variant != RPK_PIPELINED && o->variant != RPK_PCG) return RPK_ERR_ARG;
-  if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN && o->dots != RPK_DOT_FPE) return RPK_ERR_ARG;
   if (o->maxit < 0 || !(o->tol >= 0.0)) return RPK_ERR_ARG;
   Cfg c;
   RET_IF(resolve(&o->launch, A->n, &c));
@@ -391,7 +411,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   if (ws_bytes < l.total) return RPK_ERR_ARG;
   info->used.block = c.block;
   info->used.grid = c.grid;
-  info->used.fpe = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  info->used.fpe = (o->dots == RPK_DOT_PLAIN) ? 0 : (o->dots == RPK_DOT_FPE) ? LW_N : c.fpe;
   info->used.graph = c.graph;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -399,7 +419,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
 
   char* w = (char*)ws;
   const int variant = o->variant;
-  const int N = (o->dots == RPK_DOT_PLAIN) ? 0 : c.fpe;
+  const int N = kernel_n(o->dots, c.fpe);
   const int G = c.grid, B = c.block;
   const int nph = (variant == RPK_STD) ? 5 : (variant == RPK_PCG) ? 3 : 4;
   Red red = make_red(w, l, G);
@@ -442,7 +462,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   rpk_status st = RPK_OK;
   do {
     if (timing && hipEventRecord(ev[0], s) != hipSuccess) { st = RPK_ERR_HIP; break; }
-    if (!resume) st = by_fpe<InitF>(N, variant, G, B, s, Ac, V, red);
+    if (!resume) st = by_dot<InitF>(N, variant, G, B, s, Ac, V, red);
     if (st != RPK_OK) break;
     if (timing) {
       if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) { st = RPK_ERR_HIP; break; }
@@ -456,7 +476,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
     // PCG: a solve stopped at its limit after S9 still owes S10 (p := y + alpha p),
     // which opens the next iteration; a resumed solve takes it once here.
     if (resume && variant == RPK_PCG && !g_pinned->done && g_pinned->iter > 0)
-      st = by_fpe<PhaseF>(N, variant, 2, G, B, s, Ac, V, red);
+      st = by_dot<PhaseF>(N, variant, 2, G, B, s, Ac, V, red);
     if (st != RPK_OK) break;
     const bool use_graph = !timing && c.graph >= 0;
     int chunk = c.graph > 0 ? c.graph : 4;
@@ -466,7 +486,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
       if (timing) {
         for (int ph = 0; ph < nph && st == RPK_OK; ++ph) {
           if (hipEventRecord(ev[ph], s) != hipSuccess) st = RPK_ERR_HIP;
-          if (st == RPK_OK) st = by_fpe<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
+          if (st == RPK_OK) st = by_dot<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
         }
         if (st != RPK_OK) break;
         if (hipEventRecord(ev[nph], s) != hipSuccess || hipEventSynchronize(ev[nph]) != hipSuccess) {
@@ -490,7 +510,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
           rpk_status cst = RPK_OK;
           for (int k = 0; k < chunk && cst == RPK_OK; ++k)
             for (int ph = 0; ph < nph && cst == RPK_OK; ++ph)
-              cst = by_fpe<PhaseF>(N, variant, ph, G, B, cs, Ac, V, red);
+              cst = by_dot<PhaseF>(N, variant, ph, G, B, cs, Ac, V, red);
           return cst;
         }, &exec);
         if (st != RPK_OK) break;
@@ -500,7 +520,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
         const int k_iter = chunk;
         for (int k = 0; k < k_iter && st == RPK_OK; ++k)
           for (int ph = 0; ph < nph && st == RPK_OK; ++ph)
-            st = by_fpe<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
+            st = by_dot<PhaseF>(N, variant, ph, G, B, s, Ac, V, red);
         if (st != RPK_OK) break;
         launched += k_iter;
       }
@@ -531,6 +551,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   info->tau0 = h.tau0;
   info->tau = h.tau;
   info->true_res = h.true_res;
+  info->inexact_dots = h.lost;
   return (rpk_status)h.status;
 }
 

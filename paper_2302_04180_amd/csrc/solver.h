@@ -61,7 +61,7 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.tau = s->tau; d.tau0 = s->tau0; d.tol = s->tol; d.true_res = s->true_res;
   d.varsigma = s->varsigma; d.zeta = s->zeta;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
-  d.variant = s->variant; d.resumable = s->resumable; d.pad1 = 0; d.pad2 = 0;
+  d.variant = s->variant; d.resumable = s->resumable; d.lost = s->lost; d.pad2 = 0;
 }
 
 __device__ __forceinline__ void state_store(State* d, const State& s) {
@@ -287,7 +287,15 @@ __device__ __forceinline__ void publish_step(Dot<N> (&d)[K], const Shm<N>& s, co
                                              int rec) {
   if (!block_publish_last<N, K>(d, s, red, 0, rec, F & 7)) return;
   block_finalize_last<N, K>(s, red, 0);
-  if (threadIdx.x == 0) scalar_step<F>(V, s.res);
+  if (threadIdx.x == 0) {
+    if constexpr (N == LW8) {  // count the dots whose bits were not all kept
+      int c = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) c += (s.misc[1 + j] & F_LOST) ? 1 : 0;
+      if (c) V.st->lost += c;
+    }
+    scalar_step<F>(V, s.res);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -6,6 +6,7 @@ fails: there is no CPU fallback.
 """
 import ctypes
 import os
+import warnings
 
 import numpy as np
 import torch
@@ -14,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpk.so")
 
 STD, PIPELINED, PCG = 0, 1, 2
-EXACT, PLAIN = 0, 1
+EXACT, PLAIN, FPE = 0, 1, 2  # FPE: the lightweight FPE-8 dot products
 HIST_W = 12
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_ZERO_DIAG",
           5: "ERR_NONFINITE", 6: "NOT_CONVERGED", 7: "BREAKDOWN", 8: "PENDING", 9: "REJECTED"}
@@ -35,7 +36,8 @@ class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau0", ctypes.c_double),
                 ("tau", ctypes.c_double), ("true_res", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 12), ("phase_launches", ctypes.c_int32 * 12),
-                ("used", Launch), ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("used", Launch), ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("inexact_dots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -51,7 +53,7 @@ class ServerStats(ctypes.Structure):
 
 
 EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
-           "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot",
+           "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot", "rpk_fpedot",
            "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_solve_batched_workspace_bytes",
            "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
            "rpk_server_poll", "rpk_server_wait", "rpk_server_get_stats", "rpk_server_destroy",
@@ -79,6 +81,7 @@ def load(path=LIB_PATH):
     lib.rpk_matrix_dinv.argtypes = [P, ctypes.POINTER(P)]
     lib.rpk_exdot_workspace_bytes.argtypes = [I64, ctypes.POINTER(Launch), ctypes.POINTER(S)]
     lib.rpk_exdot.argtypes = [I64, P, P, P, I32, ctypes.POINTER(Launch), P, S, P]
+    lib.rpk_fpedot.argtypes = [I64, P, P, P, P, ctypes.POINTER(Launch), P, S, P]
     lib.rpk_exspmv.argtypes = [P, P, P, I32, ctypes.POINTER(Launch), P]
     lib.rpk_solve_workspace_bytes.argtypes = [P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
     lib.rpk_solve.argtypes = [P, P, P, ctypes.POINTER(Opts), P, S, P, ctypes.POINTER(Info)]
@@ -209,6 +212,30 @@ def exdot(x, y, dots=EXACT, block=0, grid=0, fpe=0):
     return out
 
 
+class InexactWarning(RuntimeWarning):
+    """A lightweight (FPE-8) dot product could not keep every bit: its result is
+    accurate but not guaranteed to be correctly rounded or reproducible; the exact
+    mode (EXACT) is the one to use for that problem."""
+
+
+def fpedot(x, y, block=0, grid=0):
+    """Lightweight dot product: returns (value, lost) as 0-dim device tensors
+    (float64, int32).  lost == 0: every bit was kept and value equals exdot bit
+    for bit; lost == 1: the result is accurate but not guaranteed."""
+    lib = load()
+    x, y = _dev(x), _dev(y)
+    assert x.numel() == y.numel()
+    L = _launch(block, grid, 0)
+    nb = ctypes.c_size_t()
+    _check(lib.rpk_exdot_workspace_bytes(x.numel(), ctypes.byref(L), ctypes.byref(nb)), "workspace")
+    ws = _workspace(nb.value, ("dot", x.device.index))
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    lost = torch.empty((), dtype=torch.int32, device=x.device)
+    _check(lib.rpk_fpedot(x.numel(), _ptr(x), _ptr(y), _ptr(out), _ptr(lost), ctypes.byref(L), _ptr(ws),
+                          ws.numel(), _stream()), "rpk_fpedot")
+    return out, lost
+
+
 def exspmv(A, x, out=None, dots=EXACT, block=0, grid=0, fpe=0):
     """y = A x with exactly rounded rows (exact mode)."""
     lib = load()
@@ -255,6 +282,9 @@ def solve(A, b, x0=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, 
     if code in (1, 2, 3):
         _check(code, "rpk_solve")
     res = _info_dict(info)
+    if info.inexact_dots:
+        warnings.warn("%d lightweight dot products could not keep every bit: the solve is not guaranteed "
+                      "reproducible; use dots=EXACT" % info.inexact_dots, InexactWarning, stacklevel=2)
     if record:
         res["hist"] = hist
     if record_xr:
@@ -268,7 +298,7 @@ def _info_dict(info):
             "tau0": info.tau0, "tau": info.tau, "true_res": info.true_res,
             "phase_ms": list(info.phase_ms), "phase_launches": list(info.phase_launches),
             "used": {"block": u.block, "grid": u.grid, "fpe": u.fpe, "graph": u.graph, "tile": u.tile},
-            "queue_ms": info.queue_ms, "latency_ms": info.latency_ms}
+            "queue_ms": info.queue_ms, "latency_ms": info.latency_ms, "inexact_dots": info.inexact_dots}
 
 
 def solve_batched(As, bs, x0s=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, grid=0, fpe=0,

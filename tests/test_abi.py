@@ -58,6 +58,12 @@ def test_host_only_entry_points(lib):
     out = ctypes.c_void_p()
     assert lib.rpk_matrix_create(0, 0, None, None, None, 0, None, ctypes.byref(out)) == 1
     assert lib.rpk_matrix_create(5, 3, None, None, None, 0, None, ctypes.byref(out)) == 1
+    # the lightweight dot refuses a missing flag pointer or workspace before any device work
+    P = ctypes.c_void_p
+    lib.rpk_fpedot.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_size_t, P]
+    assert lib.rpk_fpedot(0, None, None, P(8), None, None, P(8), 1 << 30, None) == 1
+    assert lib.rpk_fpedot(0, None, None, P(8), P(8), None, None, 1 << 30, None) == 1
+    assert lib.rpk_fpedot(-1, None, None, P(8), P(8), None, P(8), 1 << 30, None) == 1
 
 
 def test_binding_refuses_to_run_without_library(tmp_path):
