@@ -32,9 +32,9 @@ MAXIT = 5000
 # each scaled by what the same counter reads for the plain copy kernel of that
 # workload (512 MiB read + 512 MiB written).  Valid only while the kernel
 # sources still have the digest they had when the counters were taken.
-TRAFFIC = {"phase": 3, "kernel": "k_std_D<4>", "bytes": 229132640,
+TRAFFIC = {"phase": 3, "kernel": "k_std_D<4>", "bytes": 229092287,
            "fetch_scale": 1.9999, "write_scale": 1.0000,
-           "src_sha256": "d5698fd241cfd93864031811001a186486b569fbbef0e97a05cad6fe08c7f27d"}
+           "src_sha256": "15256502bfd1bec60388aa8cb8b5ddd7e770831a8d97ef298ed40fbc94813bc6"}
 
 
 KERNEL_SOURCES = ("device.h", "kernels.h", "solver.h")
@@ -81,9 +81,23 @@ def cpu_baseline(A, n_iter):
     t0 = time.perf_counter()
     res = oracle.solve(*A, b_host, tol=TOL, maxit=n_iter, variant=0)
     dt = time.perf_counter() - t0
-    return {"value": res["iters"] / dt, "unit": "iters/s", "cores": oracle.get_threads(), "kind": "oracle",
+    cores = oracle.get_threads()
+    # the same oracle on one thread, over a shorter sample
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    res1 = oracle.solve(*A, b_host, tol=TOL, maxit=2, variant=0)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": res["iters"] / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": "first %d iterations (set-up and exit residual included) of the exact standard solve "
-                      "of the same 128^3 system; %.1f s" % (res["iters"], dt)}
+                      "of the same 128^3 system; %.1f s" % (res["iters"], dt),
+            "one_core_iters_per_s": round(res1["iters"] / dt1, 3), "cpu_model": model}
 
 
 def profile_workload():
@@ -104,8 +118,8 @@ def profile_workload():
     n = N_EDGE ** 3
     M = rpk.Matrix(*A)
     b = rpk.exspmv(M, torch.ones(n, dtype=torch.float64, device="cuda"))
-    for variant in (rpk.STD, rpk.PIPELINED):
-        for dots in (rpk.EXACT, rpk.PLAIN):
+    for variant in (rpk.STD, rpk.PIPELINED, rpk.PCG):
+        for dots in (rpk.EXACT, rpk.PLAIN, rpk.FPE):
             rpk.solve(M, b, tol=TOL, maxit=20, variant=variant, dots=dots, graph=-1)
     torch.cuda.synchronize()
     M.close()
@@ -190,12 +204,14 @@ def etype_leg(torch, rpk, inputs, reps=2):
     return out
 
 
-def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, seed=2024):
+def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9, 0.5), seed=2024):
     """Open-loop Poisson arrivals of exact pipelined solves (tol 1e-9, maxit
     10000) on the request server; n log-uniform in [4096, 2.1M] (grid edge =
     round(n^(1/3)) clamped to [16, 128]), Poisson or convection-diffusion (Peclet
     U[0.1, 2]) from a seeded pool of matrices, right-hand side U(-1, 1) seeded by
-    the request id.  The arrival rate is `load` x the closed-loop saturation rate."""
+    the request id.  Arrival rates: each of `loads` x the closed-loop saturation
+    rate, one after the other on the same server (the first is reported at the
+    top level, the others under "at_<load>")."""
     import numpy as np
     rng = np.random.default_rng(seed)
     pool = []
@@ -208,7 +224,9 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
             pe = float(rng.uniform(0.1, 2.0))
             A = inputs.convdiff7(edge, (pe, pe / 2, pe / 4))
         pool.append(rpk.Matrix(*A))
-    pick = rng.integers(0, pool_size, size=warm + n_req + 64)
+    # request i draws pool matrix pick[i] and a right-hand side seeded by i: ids
+    # 0..63 measure saturation, then each load takes the next warm + n_req ids
+    pick = rng.integers(0, pool_size, size=64 + len(loads) * (warm + n_req))
     srv = rpk.Server(hbm_budget=2 << 30, max_slots=64, chunk=4, tol=1e-9, maxit=10000, variant=rpk.PIPELINED)
 
     def request(r):
@@ -219,42 +237,53 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
         return M, b, torch.zeros(M.n, dtype=torch.float64, device="cuda")
 
     # closed-loop saturation: 64 requests at once
-    reqs = [request(warm + n_req + k) for k in range(64)]
+    reqs = [request(k) for k in range(64)]
     t0 = time.perf_counter()
     ts = [srv.submit(M, b, x) for M, b, x in reqs]
     for t in ts:
         srv.wait(t)
     mu = 64 / (time.perf_counter() - t0)
-    lam = load * mu
-    gaps = rng.exponential(1.0 / lam, size=warm + n_req)
-    arrivals = np.cumsum(gaps)
-    out = {}
-    keep = {}
-    t_start = time.perf_counter()
-    r = 0
-    lat, qms, done_t = [], [], []
-    served_bytes = [0]
     check = None
-    while r < warm + n_req or out:
-        now = time.perf_counter() - t_start
-        while r < warm + n_req and arrivals[r] <= now:
-            M, b, x = request(r)
-            out[srv.submit(M, b, x)] = (r, M, b, x)
-            r += 1
-        for t in list(out):
-            res = srv.poll(t)
-            if res is None:
-                continue
-            rid, M, b, x = out.pop(t)
-            if rid >= warm:
-                served_bytes[0] += res["iters"] * (2 * (12 * M.nnz + 4 * (M.n + 1)) + 42 * 8 * M.n)
-                lat.append(res["latency_ms"])
-                qms.append(res["queue_ms"])
-                done_t.append(time.perf_counter() - t_start)
-                if check is None and res["iters"] > 20:
-                    check = (M, b, x.clone(), res)
-        time.sleep(0.0002)
-    span = max(done_t) - arrivals[warm]
+
+    def open_loop(load, id0):
+        nonlocal check
+        lam = load * mu
+        gaps = rng.exponential(1.0 / lam, size=warm + n_req)
+        arrivals = np.cumsum(gaps)
+        out = {}
+        t_start = time.perf_counter()
+        r = 0
+        lat, qms, done_t = [], [], []
+        served = 0
+        while r < warm + n_req or out:
+            now = time.perf_counter() - t_start
+            while r < warm + n_req and arrivals[r] <= now:
+                M, b, x = request(id0 + r)
+                out[srv.submit(M, b, x)] = (r, M, b, x)
+                r += 1
+            for t in list(out):
+                res = srv.poll(t)
+                if res is None:
+                    continue
+                rid, M, b, x = out.pop(t)
+                if rid >= warm:
+                    served += res["iters"] * (2 * (12 * M.nnz + 4 * (M.n + 1)) + 42 * 8 * M.n)
+                    lat.append(res["latency_ms"])
+                    qms.append(res["queue_ms"])
+                    done_t.append(time.perf_counter() - t_start)
+                    if check is None and res["iters"] > 20:
+                        check = (M, b, x.clone(), res)
+            time.sleep(0.0002)
+        span = max(done_t) - arrivals[warm]
+        lat = np.array(lat)
+        return {"offered_solves_per_s": round(lam, 1), "solves_per_s": round(n_req / span, 1),
+                "algorithmic_GBps": round(served / span / 1e9, 1),
+                "latency_ms_p50": round(float(np.percentile(lat, 50)), 2),
+                "latency_ms_p99": round(float(np.percentile(lat, 99)), 2),
+                "queue_ms_p50": round(float(np.percentile(qms, 50)), 2),
+                "queue_ms_p99": round(float(np.percentile(qms, 99)), 2)}
+
+    phases = [open_loop(ld, 64 + k * (warm + n_req)) for k, ld in enumerate(loads)]
     st = srv.stats()
     srv.close()
     same = None
@@ -264,16 +293,14 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, load=0.9, 
         same = ia["iters"] == res["iters"] and bool(torch.equal(xa, x))
     for M in pool:
         M.close()
-    lat = np.array(lat)
-    return {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
-            "offered_solves_per_s": round(lam, 1), "solves_per_s": round(n_req / span, 1),
-            "algorithmic_GBps": round(served_bytes[0] / span / 1e9, 1),
-            "latency_ms_p50": round(float(np.percentile(lat, 50)), 2),
-            "latency_ms_p99": round(float(np.percentile(lat, 99)), 2),
-            "queue_ms_p50": round(float(np.percentile(qms, 50)), 2),
-            "queue_ms_p99": round(float(np.percentile(qms, 99)), 2),
-            "hbm_budget_GiB": 2, "bytes_peak_GiB": round(st["bytes_peak"] / 2 ** 30, 2),
-            "rounds": st["rounds"], "sampled_result_equals_alone": same}
+    res = {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
+           "load": loads[0]}
+    res.update(phases[0])
+    for ld, ph in zip(loads[1:], phases[1:]):
+        res["at_%g" % ld] = ph
+    res.update({"hbm_budget_GiB": 2, "bytes_peak_GiB": round(st["bytes_peak"] / 2 ** 30, 2),
+                "rounds": st["rounds"], "sampled_result_equals_alone": same})
+    return res
 
 
 def main():
