@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, 
       st->tau = 0.0; st->tau0 = 0.0; st->tol = tol; st->true_res = 0.0;
       st->varsigma = 0.0; st->zeta = 0.0;
       st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
-      st->variant = variant; st->resumable = 0; st->lost = 0; st->pad2 = 0;
+      st->variant = variant; st->resumable = 0; st->lost = 0; st->spmv_go = 0;
     }
   }
 }

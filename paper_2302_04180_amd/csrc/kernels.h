@@ -60,8 +60,8 @@ struct State {
   double varsigma, zeta;  // pipelined: <r0,s>, <r0,z> of the current iteration (S16, taken in P1)
   int iter, maxit, done, status;
   int variant, resumable;
-  int lost;  // lightweight mode: dot products that could not keep every bit
-  int pad2;
+  int lost;     // lightweight mode: dot products that could not keep every bit
+  int spmv_go;  // pipelined: 1 when the kernel before an SpMV ran (written by that kernel only)
 };
 
 // Reduction scratch in the caller's workspace (left zeroed after every use).
@@ -523,11 +523,13 @@ __device__ __forceinline__ void lw_gather_waves(Dot<LW8>& a, const double* rec, 
   a.wave_merge(width);
 }
 
-// Returns true (in every thread) in the last workgroup to arrive.  `ticket`
-// selects the arrival counter (kernels that run one after the other may share).
+// Adds this workgroup's part of the K dots into the reduction slots slot0..
+// (record b); returns a value that depends on every atomic's result.  Alone
+// (without block_publish_last's ticket) it serves a reduction that the next
+// kernel finishes: the end of this kernel then orders the atomics before it.
 template <int N, int K>
-__device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0,
-                                                   int b, int ticket) {
+__device__ __forceinline__ unsigned long long block_publish(Dot<N> (&d)[K], const Shm<N>& s, const Red& red,
+                                                            int slot0, int b) {
   const int tid = threadIdx.x;
   unsigned long long sink = 0;
   if constexpr (N == LW8) {
@@ -614,6 +616,16 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
                                       __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  return sink;
+}
+
+// Returns true (in every thread) in the last workgroup to arrive.  `ticket`
+// selects the arrival counter (kernels that run one after the other may share).
+template <int N, int K>
+__device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>& s, const Red& red, int slot0,
+                                                   int b, int ticket) {
+  const int tid = threadIdx.x;
+  const unsigned long long sink = block_publish<N, K>(d, s, red, slot0, b);
   // using the returned values makes every thread wait until its atomics have
   // been performed before the barrier that precedes the ticket
   if (sink == 0x5bd1e9955bd1e995ull) s.misc[11] = 1;

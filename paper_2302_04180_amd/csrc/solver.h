@@ -61,7 +61,7 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.tau = s->tau; d.tau0 = s->tau0; d.tol = s->tol; d.true_res = s->true_res;
   d.varsigma = s->varsigma; d.zeta = s->zeta;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
-  d.variant = s->variant; d.resumable = s->resumable; d.lost = s->lost; d.pad2 = 0;
+  d.variant = s->variant; d.resumable = s->resumable; d.lost = s->lost; d.spmv_go = 0;
 }
 
 __device__ __forceinline__ void state_store(State* d, const State& s) {
@@ -280,6 +280,18 @@ __device__ __forceinline__ void scalar_step(const Vecs& V, const double* res) {
   state_store(V.st, S);
 }
 
+// Thread 0, after block_finalize_last: take the scalar step F on the rounded dots.
+template <int N, int K, int F>
+__device__ __forceinline__ void finish_step(const Shm<N>& s, const Vecs& V) {
+  if constexpr (N == LW8) {  // count the dots whose bits were not all kept
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) c += (s.misc[1 + j] & F_LOST) ? 1 : 0;
+    if (c) V.st->lost += c;
+  }
+  scalar_step<F>(V, s.res);
+}
+
 // Publish this workgroup's K dot partials; the last workgroup to arrive rounds
 // the dots and takes the scalar step F.
 template <int N, int K, int F>
@@ -287,15 +299,17 @@ __device__ __forceinline__ void publish_step(Dot<N> (&d)[K], const Shm<N>& s, co
                                              int rec) {
   if (!block_publish_last<N, K>(d, s, red, 0, rec, F & 7)) return;
   block_finalize_last<N, K>(s, red, 0);
-  if (threadIdx.x == 0) {
-    if constexpr (N == LW8) {  // count the dots whose bits were not all kept
-      int c = 0;
-#pragma unroll
-      for (int j = 0; j < K; ++j) c += (s.misc[1 + j] & F_LOST) ? 1 : 0;
-      if (c) V.st->lost += c;
-    }
-    scalar_step<F>(V, s.res);
-  }
+  if (threadIdx.x == 0) finish_step<N, K, F>(s, V);
+}
+
+// Publish only: the first workgroup of the following SpMV kernel rounds the dots
+// and takes the scalar step, while its other workgroups compute the SpMV, which
+// does not depend on that step (the overlap of Sec. 4.2).
+template <int N, int K, int F, bool Defer>
+__device__ __forceinline__ void publish_or_defer(Dot<N> (&d)[K], const Shm<N>& s, const Vecs& V, const Red& red,
+                                                 int rec) {
+  if constexpr (Defer) (void)block_publish<N, K>(d, s, red, 0, rec);
+  else publish_step<N, K, F>(d, s, V, red, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -530,7 +544,7 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
 }
 
 // P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
-template <int N>
+template <int N, bool Defer = false>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
@@ -560,11 +574,11 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
     d[2].add(r0, sv, s.sa + 2 * SA_D, &s.flag[2]);                    // S16: <r0,s>
     d[3].add(r0, z, s.sa + 3 * SA_D, &s.flag[3]);                     //      <r0,z>
   }
-  publish_step<N, 4, FIN_POMEGA>(d, s, V, red, rec);
+  publish_or_defer<N, 4, FIN_POMEGA, Defer>(d, s, V, red, rec);
 }
 
 // P3: S12..S15, S17 and the partials of <r0,r>, <r0,w> (S16) and <r,r> (slots 0..2)
-template <int N>
+template <int N, bool Defer = false>
 __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
@@ -589,7 +603,7 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
     d[1].add(r0, w, s.sa + SA_D, &s.flag[1]);
     d[2].add(r, r, s.sa + 2 * SA_D, &s.flag[2]);                       // tau
   }
-  publish_step<N, 3, FIN_S19>(d, s, V, red, rec);
+  publish_or_defer<N, 3, FIN_S19, Defer>(d, s, V, red, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,22 +773,53 @@ __global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
   else spmv_body<N>(A, V.zh, V.v, my_rows(A.n), s);
 }
 
+// P1 and P3 leave their reduction to the SpMV kernel that follows them
+// (k_pipe_spmv_fin), and tell its SpMV workgroups whether they ran.
 template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
+  const int done = V.st->done;
+  if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
+  if (done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
   shm_init(s, 4);
-  pipe_P1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P1_body<N, true>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
+  const int done = V.st->done;
+  if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
+  if (done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
   shm_init(s, 3);
-  pipe_P3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P3_body<N, true>(A, V, red, my_rows(A.n), blockIdx.x, s);
+}
+
+// P2 (W = 1: v = A z^, after P1, finishing S11) and P4 (W = 0: t = A w^, after
+// P3, finishing S19).  Workgroup 0 rounds the K dots P1 / P3 published and takes
+// the scalar step F; workgroups 1..gridDim.x-1 compute the SpMV, which needs
+// neither result.  The SpMV workgroups decide from spmv_go, which only the
+// kernel before wrote: `done` may change under them here.  So a P4 whose step
+// stops the solve at its iteration limit still computes the whole t (S18 of the
+// next iteration) that a resumed solve needs.
+template <int N, int W, int K, int F>
+__global__ void __launch_bounds__(1024) k_pipe_spmv_fin(Csr A, Vecs V, Red red) {
+  extern __shared__ __align__(16) char smem[];
+  if (blockIdx.x == 0) {
+    if (V.st->done) return;
+    Shm<N> s = shm_carve<N>(smem, K, true);
+    block_finalize_last<N, K>(s, red, 0);
+    if (threadIdx.x == 0) finish_step<N, K, F>(s, V);
+    return;
+  }
+  if (!V.st->spmv_go) return;
+  Shm<N> s = shm_carve<N>(smem, 0, true);
+  const int G = gridDim.x - 1;
+  const Range R = block_rows(A.n, xcd_block(blockIdx.x - 1, G), G);
+  if (W == 0) spmv_body<N>(A, V.wh, V.t, R, s);
+  else spmv_body<N>(A, V.zh, V.v, R, s);
 }
 
 template <int N>
