@@ -197,9 +197,9 @@ rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* con
                                              size_t* bytes);
 
 /* Solve nsys independent systems A[k] x[k] = b[k] (host arrays of handles and of
- * device pointers; variants RPK_STD and RPK_PIPELINED, dots RPK_DOT_EXACT or RPK_DOT_PLAIN) together: every phase of the iteration is one launch over the
+ * device pointers; variants RPK_STD, RPK_PIPELINED and RPK_PCG, dots RPK_DOT_EXACT or RPK_DOT_PLAIN) together: every phase of the iteration is one launch over the
  * rows of all systems still running, each system with its own scalars, stop
- * test and status (Fig. 2 / Fig. 3 per system, as rpk_solve).  Each system's
+ * test and status (Fig. 2 / Fig. 3 / Fig. 1 per system, as rpk_solve).  Each system's
  * iterates, scalars, iteration count and x are bit-identical to rpk_solve of
  * that system alone (the exact reductions make the grouping invisible).
  * opts: as rpk_solve; hist, when set, holds nsys * maxit * RPK_HIST_W doubles

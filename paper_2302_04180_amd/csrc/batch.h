@@ -198,6 +198,44 @@ __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   });
 }
 
+// ---------------------------------------------------------------------------
+// preconditioned CG (Fig. 1)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pcg_init(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  tile_loop<N, 2, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pcg_init_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pcg_S1(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 1, true);
+  tile_loop<N, 1, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pcg_S1_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pcg_S3(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, false);
+  tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pcg_S3_body<N>(D.A, D.V, D.red, R, rec, s);
+  });
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) kb_pcg_S10(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 0, false);
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
+                        [&](const SysDesc& D, Range R, int) { pcg_S10_body(D.V, R); });
+}
+
 // SpMVs of the pipelined loop over all tiles: W = 0: t = A w^, 1: v = A z^.
 template <int N, int W>
 __global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B) {

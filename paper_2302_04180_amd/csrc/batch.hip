@@ -101,7 +101,11 @@ SysDesc make_desc(const rpk_matrix* A, const double* b, double* x, char* base, i
   for (int j = 0; j < nvec_of(variant); ++j) p[j] = (double*)(vec + j * step);
   Vecs V;
   std::memset(&V, 0, sizeof(V));
-  V.r0 = p[0]; V.r = p[1]; V.p = p[2]; V.ph = p[3]; V.s = p[4]; V.q = p[5]; V.qh = p[6]; V.y = p[7];
+  if (variant == RPK_PCG) {  // r, p, d (in s), y
+    V.r = p[0]; V.p = p[1]; V.s = p[2]; V.y = p[3];
+  } else {
+    V.r0 = p[0]; V.r = p[1]; V.p = p[2]; V.ph = p[3]; V.s = p[4]; V.q = p[5]; V.qh = p[6]; V.y = p[7];
+  }
   if (variant == RPK_PIPELINED) {
     V.rh = p[8]; V.w = p[9]; V.wh = p[10]; V.t = p[11]; V.sh = p[12]; V.z = p[13]; V.zh = p[14]; V.v = p[15];
   }
@@ -161,7 +165,7 @@ BLayout blayout(const std::vector<int64_t>& n, int nvec, int Tcap, bool trial) {
 
 rpk_status check_opts(const rpk_opts* o) {
   if (!o) return RPK_ERR_ARG;
-  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  if (o->variant != RPK_STD && o->variant != RPK_PIPELINED && o->variant != RPK_PCG) return RPK_ERR_ARG;
   if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
   if (o->maxit < 0 || !(o->tol >= 0.0) || o->xr_hist || o->resume) return RPK_ERR_ARG;
   const rpk_launch& l = o->launch;
@@ -252,7 +256,7 @@ Shape shape_of(const Ctx& c, const BCfg& cfg, const Plan& plan) {
   sh.Gf = std::min((c.ns + 7) & ~7, 1024);
   sh.B = cfg.block;
   sh.N = (c.o->dots == RPK_DOT_PLAIN) ? 0 : cfg.fpe;
-  sh.nph = (c.o->variant == RPK_STD) ? 5 : 4;
+  sh.nph = (c.o->variant == RPK_STD) ? 5 : (c.o->variant == RPK_PCG) ? 3 : 4;
   return sh;
 }
 

@@ -76,6 +76,7 @@ template <int N>
 rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batch b) {
   (void)Gf;
   if (variant == RPK_STD) return launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b);
+  if (variant == RPK_PCG) return launch(kb_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, b);
   RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
   RET_IF(launch(kb_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, b));
   return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
@@ -97,6 +98,13 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
       case 2: return launch(kb_std_C<N>, G, B, 0, s, b);
       case 3: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
       default: return launch(kb_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+    }
+  }
+  if (variant == RPK_PCG) {
+    switch (ph) {
+      case 0: return launch(kb_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, b);
+      case 1: return launch(kb_pcg_S3<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+      default: return launch(kb_pcg_S10<N>, G, B, 0, s, b);
     }
   }
   switch (ph) {

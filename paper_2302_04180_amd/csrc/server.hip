@@ -369,7 +369,7 @@ rpk_status rpk_server_create(const rpk_server_opts* o, rpk_server** out) {
   *out = nullptr;
   const rpk_opts& so = o->solve;
   if (o->hbm_budget < 4096 || o->max_slots < 1 || o->max_slots > 65536 || o->chunk < 0) return RPK_ERR_ARG;
-  if (so.variant != RPK_STD && so.variant != RPK_PIPELINED) return RPK_ERR_ARG;
+  if (so.variant != RPK_STD && so.variant != RPK_PIPELINED && so.variant != RPK_PCG) return RPK_ERR_ARG;
   if (so.dots != RPK_DOT_EXACT && so.dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
   if (so.maxit < 0 || !(so.tol >= 0.0) || so.hist || so.xr_hist || so.timing || so.resume) return RPK_ERR_ARG;
   const rpk_launch& l = so.launch;
@@ -383,7 +383,7 @@ rpk_status rpk_server_create(const rpk_server_opts* o, rpk_server** out) {
   S->tile = l.tile ? l.tile : 4096;
   S->N = (so.dots == RPK_DOT_PLAIN) ? 0 : (l.fpe ? l.fpe : 4);
   S->nvec = nvec_of(so.variant);
-  S->nph = (so.variant == RPK_STD) ? 5 : 4;
+  S->nph = (so.variant == RPK_STD) ? 5 : (so.variant == RPK_PCG) ? 3 : 4;
   rpk_status st = RPK_OK;
   do {
     if (hipGetDevice(&S->device) != hipSuccess) { st = RPK_ERR_HIP; break; }

@@ -158,3 +158,45 @@ def test_full_batched_workload_equals_alone(orc, variant, vname):
         check_against(ro, xs[k], infos[k], hist=False)
     for M in Ms:
         M.close()
+
+
+def spd_mix(orc):
+    """Symmetric positive definite systems of uneven sizes for PCG (Fig. 1): Poisson
+    grids, a symmetric 27-point one, a power-of-two diagonal one and a 1x1 one."""
+    rp, ci, v = inputs.poisson27_etype(6)
+    sym27 = (rp, ci, np.where(v < 0, -1.0, v))
+    mats = [inputs.poisson7(4), inputs.poisson7(9), sym27, inputs.diagonal_pow2(33, 4), inputs.poisson7(3),
+            inputs.dense_to_csr(np.array([[4.0]])), inputs.poisson7(13)]
+    out = []
+    for k, A in enumerate(mats):
+        n = A[0].size - 1
+        b = orc.exspmv(*A, inputs.uniform(n, 300 + k))
+        out.append((A, rpk.Matrix(*A), b))
+    return out
+
+
+def test_batched_pcg_equals_oracle_and_alone(orc):
+    sys_ = spd_mix(orc)
+    Ms, bs = [M for _, M, _ in sys_], [T(b) for _, _, b in sys_]
+    ros = [orc.solve(*A, b, tol=TOL, maxit=MAXIT, variant=rpk.PCG, record=True) for A, _, b in sys_]
+    ref = None
+    for kw in (dict(tile=128), dict(tile=64, block=64, fpe=1, graph=-1), dict(tile=0)):
+        xs, infos = rpk.solve_batched(Ms, bs, tol=TOL, maxit=MAXIT, variant=rpk.PCG, record=True, **kw)
+        say("pcg batched", kw, "used", infos[0]["used"], [i["iters"] for i in infos])
+        for k, ((A, M, b), ro) in enumerate(zip(sys_, ros)):
+            check_against(ro, xs[k], infos[k])
+            if ref is None:
+                xa, ia = rpk.solve(M, T(b), tol=TOL, maxit=MAXIT, variant=rpk.PCG)
+                assert ia["iters"] == infos[k]["iters"] and same(H(xa), H(xs[k])), k
+        ref = True
+    # failures stay inside their system: a non-finite right-hand side and a zero one
+    bad = sys_[1][2].copy()
+    bad[5] = math.nan
+    bs2 = list(bs)
+    bs2[1] = T(bad)
+    bs2[3] = T(np.zeros(sys_[3][0][0].size - 1))
+    xs, infos = rpk.solve_batched(Ms, bs2, tol=TOL, maxit=MAXIT, variant=rpk.PCG, tile=128)
+    assert infos[1]["status"] == "ERR_NONFINITE"
+    assert infos[3]["status"] == "OK" and infos[3]["iters"] == 0
+    for k in (0, 2, 4, 5, 6):
+        assert infos[k]["iters"] == ros[k]["iters"] and same(H(xs[k]), ros[k]["x"]), k

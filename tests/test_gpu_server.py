@@ -136,3 +136,31 @@ def test_server_larger_mix_overlaps(orc):
         assert res[k]["status"] == ia["status"] == "OK"
         assert res[k]["iters"] == ia["iters"] and same(H(xs[k]), xa), k
     srv.close()
+
+
+def test_server_pcg_results_equal_alone(orc):
+    """PCG (Fig. 1) requests on SPD systems: each equals its standalone solve."""
+    rng = np.random.default_rng(31)
+    sys_ = []
+    for k in range(9):
+        A = inputs.poisson7(int(rng.integers(3, 16)))
+        n = A[0].size - 1
+        M = rpk.Matrix(*A)
+        sys_.append((A, M, H(rpk.exspmv(M, T(inputs.uniform(n, 900 + k))))))
+    srv = rpk.Server(hbm_budget=8 << 20, max_slots=4, chunk=3, tol=1e-10, maxit=500, variant=rpk.PCG, tile=256)
+    xs = [T(np.zeros(A[0].size - 1)) for A, _, _ in sys_]
+    ts = []
+    for k, (A, M, b) in enumerate(sys_):
+        ts.append(srv.submit(M, T(b), xs[k]))
+        if k % 3 == 2:
+            time.sleep(0.002)
+    res = [srv.wait(t) for t in ts]
+    assert srv.stats()["completed"] == len(sys_)
+    for k, (A, M, b) in enumerate(sys_):
+        xa, ia = alone(M, b, rpk.PCG, 1e-10, 500)
+        assert res[k]["status"] == ia["status"] == "OK" and res[k]["iters"] == ia["iters"], k
+        assert same(H(xs[k]), xa), (k, first_diff(H(xs[k]), xa))
+        if A[0].size - 1 <= 300:
+            ro = orc.solve(*A, b, tol=1e-10, maxit=500, variant=rpk.PCG)
+            assert ro["iters"] == res[k]["iters"] and same(H(xs[k]), ro["x"]), k
+    srv.close()
