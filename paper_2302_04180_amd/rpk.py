@@ -146,18 +146,42 @@ class Matrix:
     """CSR matrix handle owned by the library (device copy + Jacobi dinv)."""
 
     def __init__(self, row_ptr, col_idx, vals):
-        lib = load()
+        """Zero-based CSR arrays on the host (int32 row pointers and columns, float64 values)."""
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         v = np.ascontiguousarray(vals, dtype=np.float64)
-        self.n = rp.size - 1
-        self.nnz = ci.size
+        self._create(rp.size - 1, ci.size, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0)
+
+    def _create(self, n, nnz, p_rp, p_ci, p_v, on_device):
+        self.handle = None
+        self.n, self.nnz = int(n), int(nnz)
         h = ctypes.c_void_p()
         torch.cuda.init()
-        code = lib.rpk_matrix_create(self.n, self.nnz, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, 0,
-                                     _stream(), ctypes.byref(h))
+        code = load().rpk_matrix_create(self.n, self.nnz, p_rp, p_ci, p_v, on_device, _stream(), ctypes.byref(h))
         self.handle = h
         _check(code, "rpk_matrix_create")
+
+    @classmethod
+    def from_scipy(cls, S):
+        """From any scipy.sparse matrix (square; converted to CSR, 32-bit indices)."""
+        S = S.tocsr()
+        if S.shape[0] != S.shape[1]:
+            raise ValueError("matrix must be square")
+        if S.indptr[-1] >= 2 ** 31:
+            raise ValueError("nnz must be below 2^31")
+        return cls(S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64))
+
+    @classmethod
+    def from_tensors(cls, row_ptr, col_idx, vals):
+        """From CSR arrays already in device memory (torch tensors: int32, int32,
+        float64 on the current GPU); the library copies them device to device on
+        the current stream, after the work already queued there."""
+        for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (vals, torch.float64)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError("expected contiguous device tensors (int32, int32, float64)")
+        self = cls.__new__(cls)
+        self._create(row_ptr.numel() - 1, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), 1)
+        return self
 
     def dinv(self):
         """Copy of the Jacobi vector dinv_i = RN(1/a_ii) computed by the library."""

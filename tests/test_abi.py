@@ -82,3 +82,14 @@ def test_no_oracle_on_product_path():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt
                 assert "rpk_oracle" not in txt and "or_exdot" not in txt
+
+
+def test_binding_checks_matrix_arguments_on_the_host():
+    import scipy.sparse as sp
+    import torch
+    from paper_2302_04180_amd import rpk
+    with pytest.raises(ValueError):
+        rpk.Matrix.from_scipy(sp.csr_matrix((2, 3)))
+    with pytest.raises(ValueError):  # host tensors are not device arrays
+        rpk.Matrix.from_tensors(torch.zeros(3, dtype=torch.int32), torch.zeros(2, dtype=torch.int32),
+                                torch.zeros(2, dtype=torch.float64))

@@ -172,3 +172,24 @@ def test_device_division_and_sqrt_are_ieee():
     with np.errstate(all="ignore"):
         assert same(H(q), a / b)
         assert same(H(s), np.sqrt(a))
+
+
+def test_matrix_constructors_agree(orc):
+    """Host CSR arrays, scipy.sparse (CSR and COO) and device tensors give the same
+    matrix: the same exact SpMV and the same Jacobi vector as the oracle."""
+    import scipy.sparse as sp
+    import torch
+    rp, ci, v = inputs.convdiff7(7, (0.5, 0.25, 0.125))
+    n = rp.size - 1
+    S = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    x = inputs.uniform(n, 3)
+    ref, (jst, dref) = orc.exspmv(rp, ci, v, x), orc.jacobi(rp, ci, v)
+    assert jst == 0
+    dev = [torch.tensor(a, dtype=dt, device="cuda") for a, dt in ((rp, torch.int32), (ci, torch.int32),
+                                                                   (v, torch.float64))]
+    for M in (rpk.Matrix(rp, ci, v), rpk.Matrix.from_scipy(S), rpk.Matrix.from_scipy(S.tocoo()),
+              rpk.Matrix.from_tensors(*dev)):
+        assert M.n == n and M.nnz == ci.size
+        assert same(H(rpk.exspmv(M, T(x))), ref)
+        assert same(H(M.dinv()), dref)
+        M.close()
