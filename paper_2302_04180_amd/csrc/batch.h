@@ -37,17 +37,43 @@ struct Batch {
   const int* count;  // [0] number of tiles, [1] number of systems in `order`
 };
 
+// The tile of entry t, uniform over the workgroup: kept (and so the address of
+// its descriptor) in scalar registers.
+__device__ __forceinline__ Tile tile_at(const Batch& B, int t) {
+  return Tile{__builtin_amdgcn_readfirstlane(B.tiles[t].sys), __builtin_amdgcn_readfirstlane(B.tiles[t].lo),
+              __builtin_amdgcn_readfirstlane(B.tiles[t].hi), __builtin_amdgcn_readfirstlane(B.tiles[t].rec)};
+}
+
 // Run body(desc, rows, rec) on every tile of the table assigned to this
 // workgroup (logical index b out of G).  CHECK: skip systems that have stopped.
 template <int N, int K, bool CHECK, class Body>
 __device__ __forceinline__ void tile_loop(const Batch& B, const Shm<N>& s, int b, int G, Body body) {
   const int nt = B.count[0];
   for (int t = b; t < nt; t += G) {
-    const Tile T = B.tiles[t];
+    const Tile T = tile_at(B, t);
     if (T.sys < 0) continue;
     const SysDesc& D = B.sys[T.sys];
     if (CHECK && D.V.st->done) continue;
     if (K > 0) shm_init(s, K);
+    body(D, Range{T.lo, T.hi}, T.rec);
+    __syncthreads();
+  }
+}
+
+// P1 / P3 of the pipelined loop: the tiles only publish their partial sums (the
+// SpMV kernel after them finishes each system's reduction), and the workgroup of
+// a system's first tile records whether the system ran, for that SpMV kernel.
+template <int N, int K, class Body>
+__device__ __forceinline__ void tile_loop_publish(const Batch& B, const Shm<N>& s, int b, int G, Body body) {
+  const int nt = B.count[0];
+  for (int t = b; t < nt; t += G) {
+    const Tile T = tile_at(B, t);
+    if (T.sys < 0) continue;
+    const SysDesc& D = B.sys[T.sys];
+    const int done = D.V.st->done;
+    if (T.rec == 0 && threadIdx.x == 0) D.V.st->spmv_go = !done;
+    if (done) continue;
+    shm_init(s, K);
     body(D, Range{T.lo, T.hi}, T.rec);
     __syncthreads();
   }
@@ -184,8 +210,8 @@ template <int N>
 __global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
-  tile_loop<N, 4, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P1_body<N>(D.A, D.V, D.red, R, rec, s);
+  tile_loop_publish<N, 4>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_P1_body<N, true>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -193,9 +219,34 @@ template <int N>
 __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
-  tile_loop<N, 3, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P3_body<N>(D.A, D.V, D.red, R, rec, s);
+  tile_loop_publish<N, 3>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
+    pipe_P3_body<N, true>(D.A, D.V, D.red, R, rec, s);
   });
+}
+
+// P2 (W = 1: v = A z^, finishing S11) and P4 (W = 0: t = A w^, finishing S19)
+// over all tiles: the workgroup that takes a system's first tile first rounds
+// the K dots P1 / P3 published for that system and takes its scalar step; the
+// SpMV of every tile of a system that ran goes ahead regardless (it needs
+// neither result, and spmv_go, written by the kernel before, does not change).
+template <int N, int W, int K, int F>
+__global__ void __launch_bounds__(1024) kb_pipe_spmv_fin(Batch B) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, K, true);
+  const int nt = B.count[0];
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const Tile T = tile_at(B, t);
+    if (T.sys < 0) continue;
+    const SysDesc& D = B.sys[T.sys];
+    if (!D.V.st->spmv_go) continue;
+    if (T.rec == 0) {
+      block_finalize_last<N, K>(s, D.red, 0);
+      if (threadIdx.x == 0) finish_step<N, K, F>(s, D.V);
+    }
+    if (W == 0) spmv_body<N>(D.A, D.V.wh, D.V.t, Range{T.lo, T.hi}, s);
+    else spmv_body<N>(D.A, D.V.zh, D.V.v, Range{T.lo, T.hi}, s);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------

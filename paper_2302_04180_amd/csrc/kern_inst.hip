@@ -109,9 +109,9 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
   }
   switch (ph) {
     case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 4, false, B), s, b);
-    case 1: return launch(kb_pipe_spmv<N, 1>, G, B, shm_bytes(N, 0, true, B), s, b);
+    case 1: return launch(kb_pipe_spmv_fin<N, 1, 4, FIN_POMEGA>, G, B, shm_bytes(N, 4, true, B), s, b);
     case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 3, false, B), s, b);
-    default: return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
+    default: return launch(kb_pipe_spmv_fin<N, 0, 3, FIN_S19>, G, B, shm_bytes(N, 3, true, B), s, b);
   }
 }
 
