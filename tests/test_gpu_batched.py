@@ -130,7 +130,7 @@ def test_plain_batched_converges(orc):
         assert infos[k]["true_res"] <= 1e-8 * max(infos[k]["tau0"], 1e-300)
 
 
-@pytest.mark.parametrize("variant,vname", [(0, "std")])
+@pytest.mark.parametrize("variant,vname", [(0, "std"), (1, "pipelined")])
 def test_full_batched_workload_equals_alone(orc, variant, vname):
     """256 systems, half Poisson and half convection-diffusion, grid edges 8..48
     (tol 1e-8, maxit 500), autotuned: every system bit-identical to its own
