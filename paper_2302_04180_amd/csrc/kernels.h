@@ -292,6 +292,66 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
   return ovf ? 0.0 : fpe_round(f);
 }
 
+// Certified fast path of one row in one lane: the compensated dot product of
+// Ogita, Rump and Oishi (2005, Dot2) with its error bound.  With p_j + e_j =
+// a_j x_j (twoprod, exact for products in range) and t_j the errors of the
+// running sum s (twosum, exact), the row sum is exactly T = s + sum(t_j + e_j);
+// q = fl(sum(t_j + e_j)) is within E = gamma_k * sum(|t_j| + |e_j|) (k > 2w terms,
+// plus an allowance for underflow) of that sum.  With (y, r) = twosum(s, q),
+// T = y + r + d with |d| <= E, so y = RN(T) whenever |r| + E is below half the
+// gap from y to its neighbours.  Returns false -- the caller then takes the FPE
+// path -- when that cannot be shown, or for a sum that is zero, tiny, huge or
+// not finite, or a product out of range.  When it returns true, y is the
+// correctly rounded row sum: the same bits as the FPE path.
+template <class Gth>
+__device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const int* __restrict__ scol, const Gth& gx,
+                                         int w, double& y) {
+  double s = 0.0, q = 0.0, m = 0.0;
+  bool ok = true;
+  for (int j0 = 0; j0 < w; j0 += 8) {
+    double a[8], b[8];
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = j0 + u < w;
+      a[u] = in ? __builtin_nontemporal_load(sval + (size_t)(j0 + u) * 64) : 0.0;
+      c[u] = in ? __builtin_nontemporal_load(scol + (size_t)(j0 + u) * 64) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double p = a[u] * b[u];
+      const double ap = fabs(p);
+      ok &= (ap >= kProdLo && ap < kProdHi) || (p == 0.0 && (a[u] == 0.0 || b[u] == 0.0));
+      const double e = fma(a[u], b[u], -p);
+      const double s1 = s + p;
+      const double z = s1 - s;
+      const double t = (s - (s1 - z)) + (p - z);
+      s = s1;
+      q += t;
+      q += e;
+      m += fabs(t) + fabs(e);
+    }
+  }
+  const double k = 2.0 * w + 2.0;
+  const double E = (m * (k * 0x1p-53)) * (1.0 + 0x1p-28) + k * 0x1p-1074;
+  const double y0 = s + q;
+  const double z = y0 - s;
+  const double r = (s - (y0 - z)) + (q - z);
+  y = y0;
+  const double ay = fabs(y0);
+  if (!ok || !(ay >= 0x1p-960) || !(ay < 0x1p1020)) return false;
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(ay);
+  const double up = __longlong_as_double((long long)(bits + 1ull)) - ay;  // spacing above |y|
+  const bool pow2 = (bits & ((1ull << 52) - 1ull)) == 0ull;               // then the spacing below is up / 2
+  const double half = pow2 ? 0.25 * up : 0.5 * up;
+  return (fabs(r) + E) * (1.0 + 0x1p-50) < half;
+}
+
+// slice width from which rows try row_cert first
+constexpr int kCertMinWidth = 16;
+
 // Exact slow path: the whole wavefront sums one row (entries at sv[64 j],
 // sc[64 j]) in its private long accumulator through exact integer products;
 // lane 0 rounds it.
@@ -348,8 +408,17 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     }
     return acc;
   } else {
+    double y = 0.0;
+    // wide rows: try the certified compensated sum first (its dependency chain
+    // is about two additions per entry, an FPE insertion's several twosums);
+    // narrow rows go straight to the FPE, which is cheaper there (short rows
+    // often sum exactly to a rounding midpoint, which the bound cannot decide)
+    if (w >= kCertMinWidth) {
+      const bool cert = row_cert(sv, sc, gx, w, y);
+      if (__ballot(valid && !cert) == 0ull) return y;
+    }
     bool bad = false;
-    double y = row_fast<kRowN<N>>(sv, sc, gx, w, bad);
+    y = row_fast<kRowN<N>>(sv, sc, gx, w, bad);
     bad = bad && valid;
     unsigned long long m = __ballot(bad);
     if (m) {

@@ -193,3 +193,39 @@ def test_matrix_constructors_agree(orc):
         assert same(H(rpk.exspmv(M, T(x))), ref)
         assert same(H(M.dinv()), dref)
         M.close()
+
+
+def test_rows_at_and_near_rounding_boundaries(orc):
+    """Row sums placed exactly on, just above and just below the midpoint between
+    two doubles (powers of two included, where the gap below is half the gap
+    above), with tiny, cancelling and wide-range terms: every row equals the
+    oracle's correctly rounded sum, whichever path the kernel takes for it."""
+    rng = np.random.default_rng(77)
+    n = 4096
+    base = np.ldexp(rng.uniform(1.0, 2.0, n), rng.integers(-40, 40, n))
+    base[::7] = np.ldexp(1.0, rng.integers(-40, 40, n))[::7]          # powers of two
+    base *= np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    ulp = np.spacing(np.abs(base))
+    sign = np.sign(base)
+    kind = rng.integers(0, 8, n)
+    h = np.where(kind % 2 == 0, 0.5, -0.25) * ulp * sign                 # half-gap above or below (pow2 side)
+    tiny = np.select([kind < 2, kind < 4, kind < 6], [0.0, ulp * 2.0 ** -40, -ulp * 2.0 ** -40],
+                     np.ldexp(1.0, -1000))
+    tiny = np.where(tiny == 0.0, 0.0, tiny * np.where(rng.random(n) < 0.5, -1.0, 1.0))
+    big = np.where(rng.random(n) < 0.3, np.ldexp(1.0, 60) * sign, 0.0)  # cancels exactly
+    rows = []
+    for i in range(n):
+        ents = {i: base[i], (i + 1) % n: h[i], (i + 2) % n: tiny[i] if tiny[i] != 0.0 else 0.0}
+        if big[i] != 0.0:
+            ents[(i + 3) % n] = big[i]
+            ents[(i + 4) % n] = -big[i]
+        rows.append(sorted((c, v) for c, v in ents.items() if v != 0.0 or c == i))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c, _ in r], dtype=np.int32)
+    v = np.array([v for r in rows for _, v in r], dtype=np.float64)
+    M = rpk.Matrix(rp, ci, v)
+    for x in (np.ones(n), rng.uniform(0.5, 1.5, n)):
+        got, ref = H(rpk.exspmv(M, T(x))), orc.exspmv(rp, ci, v, x)
+        assert same(got, ref), first_diff(got, ref)
+    M.close()
