@@ -287,15 +287,14 @@ __global__ void __launch_bounds__(1024) kb_pcg_S10(Batch B) {
                         [&](const SysDesc& D, Range R, int) { pcg_S10_body(D.V, R); });
 }
 
-// SpMVs of the pipelined loop over all tiles: W = 0: t = A w^, 1: v = A z^.
-template <int N, int W>
+// Third set-up step of the pipelined loop over all tiles: t = A w^ (the loop's
+// own SpMVs are kb_pipe_spmv_fin).
+template <int N>
 __global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, true);
-  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int) {
-    if (W == 0) spmv_body<N>(D.A, D.V.wh, D.V.t, R, s);
-    else spmv_body<N>(D.A, D.V.zh, D.V.v, R, s);
-  });
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
+                        [&](const SysDesc& D, Range R, int) { spmv_body<N>(D.A, D.V.wh, D.V.t, R, s); });
 }
 
 }  // namespace rpk

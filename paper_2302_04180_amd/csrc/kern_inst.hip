@@ -28,7 +28,7 @@ rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V
   if (variant == RPK_PCG) return launch(k_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-  return launch(k_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, A, V);
+  return launch(k_pipe_spmv<N>, G, B, shm_bytes(N, 0, true, B), s, A, V);
 }
 
 template <int N>
@@ -79,7 +79,7 @@ rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batc
   if (variant == RPK_PCG) return launch(kb_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, b);
   RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
   RET_IF(launch(kb_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-  return launch(kb_pipe_spmv<N, 0>, G, B, shm_bytes(N, 0, true, B), s, b);
+  return launch(kb_pipe_spmv<N>, G, B, shm_bytes(N, 0, true, B), s, b);
 }
 
 template <int N>

@@ -761,16 +761,15 @@ __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
   pipe_init2_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-// The SpMVs of the pipelined loop: W = 0: t = A w^ (set-up 3 and S18), 1: v = A z^ (S10).
-// S18 belongs to the iteration after S19: it still runs after a stop at the
-// iteration limit, so that a resumed solve finds t in place.
-template <int N, int W>
+// Third set-up step of the pipelined loop: t = A w^ (the loop's own SpMVs are
+// k_pipe_spmv_fin below).  It still runs when the set-up stops at an iteration
+// limit of 0, so that a resumed solve finds t in place.
+template <int N>
 __global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
-  if (V.st->done && !(W == 0 && V.st->resumable == 1)) return;
+  if (V.st->done && V.st->resumable != 1) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, true);
-  if (W == 0) spmv_body<N>(A, V.wh, V.t, my_rows(A.n), s);
-  else spmv_body<N>(A, V.zh, V.v, my_rows(A.n), s);
+  spmv_body<N>(A, V.wh, V.t, my_rows(A.n), s);
 }
 
 // P1 and P3 leave their reduction to the SpMV kernel that follows them
