@@ -231,8 +231,10 @@ typedef struct {
                           allocation made at creation)                        */
   int32_t max_slots;   /* solves in flight at most, 1 .. 65536                */
   int32_t chunk;       /* iterations between admission points; 0 = 4          */
-  rpk_opts solve;      /* tol, maxit, variant, dots and launch.block / fpe /
-                          tile of every request; hist, xr_hist, timing: 0     */
+  rpk_opts solve;      /* tol, maxit, variant (RPK_STD, RPK_PIPELINED or
+                          RPK_PCG), dots (RPK_DOT_EXACT or RPK_DOT_PLAIN) and
+                          launch.block / fpe / tile of every request; hist,
+                          xr_hist, timing, resume: 0                          */
 } rpk_server_opts;
 
 typedef struct {
