@@ -4,7 +4,8 @@
 // Iakymchuk & Aliaga, Sec. 2 and Sec. 3.2:
 //   * error-free transformations twosum (Alg. 1) and twoprod via fma (Alg. 2);
 //   * a per-lane floating-point expansion (FPE) of N doubles filled by a twosum
-//     cascade with early exit (the "lightweight" FPE of Sec. 3.2);
+//     cascade (with a wave-uniform early exit for row sums; run through for dot
+//     products, where that overlaps better), the FPE of Sec. 3.2;
 //   * a Kulisch-style long accumulator (Sec. 2) of 64-bit integer digits that
 //     receives whatever an FPE cannot hold, merged with integer atomics in LDS
 //     and in global memory (Sec. 3.2: long accumulators reduce as plain integer
@@ -58,30 +59,18 @@ __device__ __forceinline__ void fpe_zero(Fpe<N>& f) {
   for (int k = 0; k < N; ++k) f.c[k] = 0.0;
 }
 
-// Insert x with a twosum cascade, stopping as soon as the carried error is 0.
+// Insert x with a twosum cascade from component S through every component.
 // Returns the part that did not fit (0.0 if absorbed); the FPE sum plus the
-// returned value equals the old sum plus x exactly.
-template <int N>
-__device__ __forceinline__ double fpe_add(Fpe<N>& f, double x) {
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    if (x == 0.0) break;
-    double r, s;
-    two_sum(f.c[k], x, r, s);
-    f.c[k] = r;
-    x = s;
-  }
-  return x;
-}
-
-// Same cascade starting at component S: used for the twoprod error terms,
-// which are too small to change the leading component.  Any start level keeps
-// the sum exact; the choice only shortens the cascade.
+// returned value equals the old sum plus x exactly.  A level with x = 0 leaves
+// its component unchanged, so running every level gives the same FPE as
+// stopping early; without the data-dependent exits the cascades of successive
+// products overlap (the dot-product accumulators use it).  Starting at S = 1
+// suits the twoprod error terms, too small to change the leading component;
+// any start level keeps the sum exact.
 template <int N, int S>
-__device__ __forceinline__ double fpe_add_from(Fpe<N>& f, double x) {
+__device__ __forceinline__ double fpe_add_all(Fpe<N>& f, double x) {
 #pragma unroll
   for (int k = S; k < N; ++k) {
-    if (x == 0.0) break;
     double r, s;
     two_sum(f.c[k], x, r, s);
     f.c[k] = r;
@@ -94,7 +83,8 @@ __device__ __forceinline__ double fpe_add_from(Fpe<N>& f, double x) {
 // only when no lane of the wavefront still carries a non-zero error; otherwise
 // every lane runs it (a twosum with x = 0 leaves the component's value
 // unchanged), which avoids per-lane control flow.  Same exact result as
-// fpe_add_from<N, S>; only the instruction count differs.
+// fpe_add_all<N, S>; only the instruction count differs (the row sums use it:
+// their error terms are often 0 for every lane).
 template <int N, int S>
 __device__ __forceinline__ double fpe_add_w(Fpe<N>& f, double x) {
 #pragma unroll
@@ -450,8 +440,8 @@ __device__ __forceinline__ void acc_prod(Fpe<N>& f, double a, double b, long lon
   // and are handled below
   const bool ok = ap >= kProdLo && ap < kProdHi;
   const double e = ok ? fma(a, b, -p) : 0.0;
-  const double l1 = fpe_add_w<N, 0>(f, ok ? p : 0.0);
-  const double l2 = fpe_add_w<N, (N > 1 ? 1 : 0)>(f, e);
+  const double l1 = fpe_add_all<N, 0>(f, ok ? p : 0.0);
+  const double l2 = fpe_add_all<N, (N > 1 ? 1 : 0)>(f, e);
   const bool extreme = !ok && !(p == 0.0 && (a == 0.0 || b == 0.0));
   if (l1 != 0.0 || l2 != 0.0 || extreme) {
     if (l1 != 0.0 || l2 != 0.0) {
