@@ -177,7 +177,8 @@ def batched_leg(torch, rpk, inputs, reps=3):
 def etype_leg(torch, rpk, inputs, reps=2):
     """The paper's scalability workload on one GPU: nonsymmetric 27-point 'e-type'
     Poisson 159^3 (n = 4,019,679), b = A*1, x0 = 0, tol 1e-6 (the paper's
-    tolerance), exact and plain, standard and pipelined."""
+    tolerance), exact and plain, standard and pipelined; and PCG on its symmetric
+    counterpart."""
     A = inputs.poisson27_etype(159)
     M = rpk.Matrix(*A)
     n, nnz = M.n, M.nnz
@@ -200,6 +201,29 @@ def etype_leg(torch, rpk, inputs, reps=2):
             out["%s_%s" % (vname, dname)] = {"iters_per_s": round(ips, 1), "iterations": info["iters"],
                                              "status": info["status"], "algorithmic_GBps": round(gbs, 1),
                                              "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    M.close()
+    # PCG (Fig. 1) on the symmetric 27-point Poisson of the same size (the e-type
+    # stencil without its perturbation), b = A*1, tol 1e-6: one SpMV and 13 vector
+    # streams per iteration
+    A = inputs.poisson27(159)
+    M = rpk.Matrix(*A)
+    del A
+    b = rpk.exspmv(M, torch.ones(n, dtype=torch.float64, device="cuda"))
+    csr = 12 * M.nnz + 4 * (n + 1)
+    for dots, dname in ((rpk.EXACT, "exact"), (rpk.PLAIN, "plain")):
+        rpk.solve(M, b, tol=1e-6, maxit=5000, variant=rpk.PCG, dots=dots)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = 0
+        for _ in range(reps):
+            x, info = rpk.solve(M, b, tol=1e-6, maxit=5000, variant=rpk.PCG, dots=dots)
+            it += info["iters"]
+        torch.cuda.synchronize()
+        ips = it / (time.perf_counter() - t0)
+        gbs = ips * (csr + 13 * 8 * n) / 1e9
+        out["sym27_pcg_%s" % dname] = {"iters_per_s": round(ips, 1), "iterations": info["iters"],
+                                       "status": info["status"], "algorithmic_GBps": round(gbs, 1),
+                                       "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
     M.close()
     return out
 

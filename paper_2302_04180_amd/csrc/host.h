@@ -21,6 +21,7 @@ struct rpk_matrix {
   long long* sptr = nullptr;
   int* scol = nullptr;
   double* sval = nullptr;
+  int cert = 0;                    // rows of wide slices try the certified sum (see Csr)
 };
 
 namespace rpkhost {
@@ -35,7 +36,7 @@ using namespace rpk;
 constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n}; }
+inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert}; }
 
 inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK_PCG ? 4 : 16; }
 

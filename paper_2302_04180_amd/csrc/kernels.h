@@ -50,6 +50,9 @@ struct Csr {
   const double* sval;     // [sptr[nslices]]
   const double* dinv;
   int n;
+  // 1: rows of wide slices try the certified row sum first (decided once per
+  // matrix at creation by a probe; both paths give the same bits)
+  int cert;
 };
 
 // Device-resident solver state (one per solve, in the caller's workspace).
@@ -337,6 +340,10 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
   const double k = 2.0 * w + 2.0;
   const double E = (m * (k * 0x1p-53)) * (1.0 + 0x1p-28) + k * 0x1p-1074;
   const double y0 = s + q;
+  if (ok && m == 0.0) {  // every error term is 0: the sum is s exactly (+0 for a zero row)
+    y = y0;
+    return true;
+  }
   const double z = y0 - s;
   const double r = (s - (y0 - z)) + (q - z);
   y = y0;
@@ -349,7 +356,7 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
   return (fabs(r) + E) * (1.0 + 0x1p-50) < half;
 }
 
-// slice width from which rows try row_cert first
+// slice width from which rows may try row_cert first
 constexpr int kCertMinWidth = 16;
 
 // Exact slow path: the whole wavefront sums one row (entries at sv[64 j],
@@ -413,7 +420,7 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     // is about two additions per entry, an FPE insertion's several twosums);
     // narrow rows go straight to the FPE, which is cheaper there (short rows
     // often sum exactly to a rounding midpoint, which the bound cannot decide)
-    if (w >= kCertMinWidth) {
+    if (A.cert && w >= kCertMinWidth) {
       const bool cert = row_cert(sv, sc, gx, w, y);
       if (__ballot(valid && !cert) == 0ull) return y;
     }

@@ -243,6 +243,35 @@ static rpk_status build_sell(rpk_matrix* A, hipStream_t s) {
   return st;
 }
 
+// Whether rows of wide slices should try the certified row sum first: probe it
+// on a pseudo-random vector and keep it when at most one wide slice in eight
+// has a row it cannot certify (results are the same either way).
+static rpk_status probe_cert(rpk_matrix* A, hipStream_t s) {
+  A->cert = 0;
+  double* x = nullptr;
+  unsigned* counts = nullptr;
+  if (hipMalloc((void**)&x, (size_t)A->n * sizeof(double)) != hipSuccess) return RPK_ERR_NOMEM;
+  if (hipMalloc((void**)&counts, 2 * sizeof(unsigned)) != hipSuccess) {
+    (void)hipFree(x);
+    return RPK_ERR_NOMEM;
+  }
+  rpk_status st = RPK_OK;
+  unsigned h[2] = {0u, 0u};
+  do {
+    if (hipMemsetAsync(counts, 0, 2 * sizeof(unsigned), s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    hipLaunchKernelGGL(k_fill_hash, dim3(1024), dim3(256), 0, s, x, (long long)A->n);
+    const long long threads = (long long)A->nslices * 64;
+    hipLaunchKernelGGL(k_cert_probe, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, csr_of(A), x, counts);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    A->cert = (h[1] > 0 && 8ull * h[0] <= h[1]) ? 1 : 0;
+  } while (0);
+  (void)hipFree(x);
+  (void)hipFree(counts);
+  return st;
+}
+
 static rpk_status create_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
                               int32_t on_dev, hipStream_t s, rpk_matrix* A) {
   A->n = n;
@@ -281,7 +310,8 @@ static rpk_status create_impl(int64_t n, int64_t nnz, const int32_t* rp, const i
   } while (0);
   (void)hipFree(flags);
   if (st != RPK_OK) return st;
-  return build_sell(A, s);
+  RET_IF(build_sell(A, s));
+  return probe_cert(A, s);
 }
 
 rpk_status rpk_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,

@@ -97,6 +97,40 @@ __global__ void k_fill_sell(const int* rp, const int* ci, const double* v, int n
   }
 }
 
+// Probe at matrix creation: one wavefront per slice of at least kCertMinWidth
+// entries tries row_cert on x; counts[0] += slices where some row was not
+// certified, counts[1] += slices tried.  Rows whose sums often land exactly on a
+// rounding midpoint (many exact products) fail it, and there both paths would
+// run: the matrix then leaves it off.
+__global__ void __launch_bounds__(256) k_cert_probe(Csr A, const double* __restrict__ x, unsigned* counts) {
+  const int nslices = (A.n + 63) >> 6;
+  const int s = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  if (s >= nslices) return;  // whole wavefronts (blockDim.x is a multiple of 64)
+  const int lane = threadIdx.x & 63;
+  const long long off = A.sptr[s];
+  const int w = (int)((A.sptr[s + 1] - off) >> 6);
+  if (w < kCertMinWidth) return;
+  double y;
+  const bool valid = (s << 6) + lane < A.n;
+  const bool cert = row_cert(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
+  const bool fail = __ballot(valid && !cert) != 0ull;
+  if (lane == 0) {
+    atomicAdd(&counts[1], 1u);
+    if (fail) atomicAdd(&counts[0], 1u);
+  }
+}
+
+// x[i] in [-1, 1) from a 64-bit mix of i (the certified-row probe's input)
+__global__ void k_fill_hash(double* x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+  }
+}
+
 __global__ void k_fill(double* p, long long n, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;

@@ -69,12 +69,22 @@ def poisson27_etype(N):
     natural ordering: diagonal 26, every neighbour -1, except that the entries
     below the diagonal (column < row) are -(1.0 - 0.0001) (the perturbation of
     the scalability workload of Sec. 5).  N = 159 gives n = 4,019,679."""
+    return _poisson27(N, -(1.0 - 0.0001))
+
+
+def poisson27(N):
+    """Symmetric positive definite 27-point 3D Poisson on an N^3 grid (the e-type
+    stencil without its perturbation: diagonal 26, every neighbour -1), for the
+    preconditioned CG of Fig. 1."""
+    return _poisson27(N, -1.0)
+
+
+def _poisson27(N, lower):
     n = N ** 3
     idx = np.arange(n, dtype=np.int64)
     x = idx % N
     y = (idx // N) % N
     z = idx // (N * N)
-    lower = -(1.0 - 0.0001)
     offs, masks, vals = [], [], []
     for dz in (-1, 0, 1):
         mz = (z > 0) if dz < 0 else (z < N - 1) if dz > 0 else None

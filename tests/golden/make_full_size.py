@@ -8,7 +8,8 @@ with b = A*1 and the random banded matrix (n = 500,000, 20 entries per row),
 both pipelined, tol 1e-9, maxit 10000; the nonsymmetric 27-point 'e-type'
 Poisson 159^3 (n = 4,019,679) with b = A*1, tol 1e-6, maxit 5000, standard and
 pipelined; the 128^3 Poisson with the preconditioned conjugate gradient of
-Fig. 1 (tol 1e-10).  Stored per case: SHA-256 of the input
+Fig. 1 (tol 1e-10), and the same on the symmetric 27-point Poisson 159^3
+(b = A*1, tol 1e-6).  Stored per case: SHA-256 of the input
 arrays, status, iteration count, tau0, tau, true residual, every recorded
 iteration scalar (hex), SHA-256 of the solution's bytes and a few solution
 entries (hex).
@@ -42,6 +43,7 @@ def cases():
         "etype159_std": (lambda: inputs.poisson27_etype(159), 0, 1e-6, 5000),
         "etype159_pipelined": (lambda: inputs.poisson27_etype(159), 1, 1e-6, 5000),
         "poisson128_pcg": (lambda: inputs.poisson7(128), 2, 1e-10, 5000),
+        "sym27_159_pcg": (lambda: inputs.poisson27(159), 2, 1e-6, 5000),
     }
 
 

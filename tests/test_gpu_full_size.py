@@ -25,6 +25,7 @@ MATRICES = {
     "etype159_std": lambda: inputs.poisson27_etype(159),
     "etype159_pipelined": lambda: inputs.poisson27_etype(159),
     "poisson128_pcg": lambda: inputs.poisson7(128),
+    "sym27_159_pcg": lambda: inputs.poisson27(159),
 }
 
 
