@@ -135,7 +135,9 @@ const char* rpk_status_str(int32_t status);
  * 0 <= col < n (else RPK_ERR_ARG); finite values (else RPK_ERR_NONFINITE);
  * exactly one diagonal entry per row, non-zero (else RPK_ERR_ZERO_DIAG).  The
  * Jacobi preconditioner dinv_i = RN(1/a_ii) (Sec. 4, M = diag(A)) is computed on
- * the device.  Columns within a row may come in any order and off-diagonal
+ * the device, and a short probe decides whether rows of 16 or more entries first
+ * try a certified compensated sum (a speed choice only: every row sum is the
+ * correctly rounded exact sum either way).  Columns within a row may come in any order and off-diagonal
  * duplicates are summed exactly.  1 <= n < 2^31, 0 <= nnz < 2^31.
  * ptrs_on_device: 0 = host arrays, 1 = device arrays.  Synchronous.
  * On error *out is NULL and nothing is leaked. */

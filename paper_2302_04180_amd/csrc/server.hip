@@ -200,8 +200,7 @@ rpk_status upload(rpk_server* S) {
 }
 
 int gf_of(size_t ns) { return (int)std::min<size_t>((ns + 7) & ~size_t(7), 1024); }
-// tile-walking workgroups: one per tile up to a limit (a multiple of 8 that leaves
-// room for the finishing workgroups of the pipelined SpMV launches)
+// tile-walking workgroups: one per tile up to a limit
 int g_of(int ntiles) { return std::min(ntiles, 64000); }
 
 template <int N>

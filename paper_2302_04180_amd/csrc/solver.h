@@ -11,15 +11,16 @@
 //   C: S4 + S5
 //   D: S6 SpMV (gathers q^) + S7                  -> last workgroup: omega
 //   E: S8 + S9, S10/S11                           -> last workgroup: tau, stop test, beta
-// Pipelined loop, four kernels per iteration.  The reductions of Fig. 3 are
-// finished at the end of the kernel that produces their terms, so on one GPU
-// there is no latency left for the SpMVs to hide:
-//   P1: S1..S7 + S9 + S8, and <r0,s>, <r0,z> of S16 -> last workgroup: omega (S11)
-//   P2: S10 SpMV
-//   P3: S12..S15 + S17 + the rest of S16 (and <r,r> for tau) -> last workgroup: S19
+// Pipelined loop, four kernels per iteration.  Each reduction of Fig. 3 is
+// published by the kernel that produces its terms and finished by workgroup 0
+// of the SpMV kernel after it, while that kernel's other workgroups compute the
+// SpMV, which does not need the result (the overlap of Sec. 4.2):
+//   P1: S1..S7 + S9 + S8, and <r0,s>, <r0,z> of S16 -> published
+//   P2: S10 SpMV                                    | workgroup 0: omega (S11)
+//   P3: S12..S15 + S17 + the rest of S16 (and <r,r> for tau) -> published
+//   P4: S18 SpMV                                    | workgroup 0: S19
 // s and z do not change between S2/S4 and S16, so their two S16 dots are taken
 // where they are produced (P1 reads r0 once instead of P3 reading s and z).
-//   P4: S18 SpMV
 // Every update is the explicit fma written next to it; scalar steps are single
 // IEEE operations in one thread, in the order of the figures.
 #pragma once
