@@ -102,8 +102,11 @@ def test_midpoint_rows_are_declined():
     # cannot settle it, so the certificate declines (the FPE path rounds it)
     ok, _ = certify([1.0, 2.0 ** -53], [1.0, 1.0])
     assert not ok
-    # 2^-80 above or below it: provably on one side, certified to the right neighbour
+    # 2^-80 above it: provably on the upper side, certified to 1 + 2^-52
     assert certify([1.0, 2.0 ** -53, 2.0 ** -80], [1.0, 1.0, 1.0]) == (True, 1.0 + 2.0 ** -52)
-    assert certify([1.0, 2.0 ** -53, -(2.0 ** -80)], [1.0, 1.0, 1.0]) == (True, 1.0)
+    # 2^-80 below it: the sum rounds to 1, a power of two, where the test takes the
+    # smaller gap (below) on both sides; it may decline, and if not, gives 1
+    ok, y = certify([1.0, 2.0 ** -53, -(2.0 ** -80)], [1.0, 1.0, 1.0])
+    assert not ok or y == 1.0
     # all error terms zero: exact, certified even at zero
     assert certify([2.0, -2.0], [1.5, 1.5]) == (True, 0.0)
