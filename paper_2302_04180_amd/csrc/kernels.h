@@ -50,8 +50,9 @@ struct Csr {
   const double* sval;     // [sptr[nslices]]
   const double* dinv;
   int n;
-  // 1: rows of wide slices try the certified row sum first (decided once per
-  // matrix at creation by a probe; both paths give the same bits)
+  // rows first try the certified row sum: 0 = no, 1 = with the error bound,
+  // 2 = also accepting an exactly accumulated correction (decided once per
+  // matrix at creation by a probe; every path gives the same bits)
   int cert;
 };
 
@@ -302,15 +303,18 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
 // q = fl(sum(t_j + e_j)) is within E = gamma_k * sum(|t_j| + |e_j|) (k > 2w terms,
 // plus an allowance for underflow) of that sum.  With (y, r) = twosum(s, q),
 // T = y + r + d with |d| <= E, so y = RN(T) whenever |r| + E is below half the
-// gap from y to its neighbours.  Returns false -- the caller then takes the FPE
-// path -- when that cannot be shown, or for a sum that is zero, tiny, huge or
-// not finite, or a product out of range.  When it returns true, y is the
-// correctly rounded row sum: the same bits as the FPE path.
-template <class Gth>
+// gap from y to its neighbours.  Track: also check with twosum that every
+// addition into q was exact; then T = s + q and y = RN(s + q) is RN(T) even
+// when T is a rounding midpoint, which no bound can settle (sums of a few
+// exact products often are).  Returns false -- the caller then takes the FPE
+// path -- when neither shows it, or for a product out of range or a sum that
+// is non-finite or, for the bound, zero, tiny or huge.  When it returns true, y
+// is the correctly rounded row sum: the same bits as the FPE path.
+template <bool Track, class Gth>
 __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const int* __restrict__ scol, const Gth& gx,
                                          int w, double& y) {
   double s = 0.0, q = 0.0, m = 0.0;
-  bool ok = true;
+  bool ok = true, exactq = true;
   for (int j0 = 0; j0 < w; j0 += 8) {
     double a[8], b[8];
     int c[8];
@@ -332,10 +336,25 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
       const double z = s1 - s;
       const double t = (s - (s1 - z)) + (p - z);
       s = s1;
-      q += t;
-      q += e;
+      if constexpr (Track) {
+        const double q1 = q + t;
+        double zq = q1 - q;
+        const double et = (q - (q1 - zq)) + (t - zq);
+        const double q2 = q1 + e;
+        zq = q2 - q1;
+        const double ee = (q1 - (q2 - zq)) + (e - zq);
+        q = q2;
+        exactq &= (et == 0.0) & (ee == 0.0);
+      } else {
+        q += t;
+        q += e;
+      }
       m += fabs(t) + fabs(e);
     }
+  }
+  if (Track && ok && exactq) {  // q is the exact sum of the error terms
+    y = s + q;
+    return true;
   }
   const double k = 2.0 * w + 2.0;
   const double E = (m * (k * 0x1p-53)) * (1.0 + 0x1p-28) + k * 0x1p-1074;
@@ -355,9 +374,6 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
   const double half = pow2 ? 0.25 * up : 0.5 * up;
   return (fabs(r) + E) * (1.0 + 0x1p-50) < half;
 }
-
-// slice width from which rows may try row_cert first
-constexpr int kCertMinWidth = 16;
 
 // Exact slow path: the whole wavefront sums one row (entries at sv[64 j],
 // sc[64 j]) in its private long accumulator through exact integer products;
@@ -416,12 +432,11 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     return acc;
   } else {
     double y = 0.0;
-    // wide rows: try the certified compensated sum first (its dependency chain
-    // is about two additions per entry, an FPE insertion's several twosums);
-    // narrow rows go straight to the FPE, which is cheaper there (short rows
-    // often sum exactly to a rounding midpoint, which the bound cannot decide)
-    if (A.cert && w >= kCertMinWidth) {
-      const bool cert = row_cert(sv, sc, gx, w, y);
+    // try the certified compensated sum first where the matrix's probe chose
+    // it: its dependency chain is a few additions per entry, an FPE
+    // insertion's several twosums with a data-dependent exit after each
+    if (A.cert) {
+      const bool cert = (A.cert == 2) ? row_cert<true>(sv, sc, gx, w, y) : row_cert<false>(sv, sc, gx, w, y);
       if (__ballot(valid && !cert) == 0ull) return y;
     }
     bool bad = false;

@@ -244,29 +244,30 @@ static rpk_status build_sell(rpk_matrix* A, hipStream_t s) {
   return st;
 }
 
-// Whether rows of wide slices should try the certified row sum first: probe it
-// on a pseudo-random vector and keep it when at most one wide slice in eight
-// has a row it cannot certify (results are the same either way).
+// Whether and how rows should try the certified row sum first: probe it on a
+// pseudo-random vector and take the cheaper form (bound only, then with the
+// exactness check) under which at most one slice in eight has a row it cannot
+// certify; neither, when both fail more often (results are the same either way).
 static rpk_status probe_cert(rpk_matrix* A, hipStream_t s) {
   A->cert = 0;
   double* x = nullptr;
   unsigned* counts = nullptr;
   if (hipMalloc((void**)&x, (size_t)A->n * sizeof(double)) != hipSuccess) return RPK_ERR_NOMEM;
-  if (hipMalloc((void**)&counts, 2 * sizeof(unsigned)) != hipSuccess) {
+  if (hipMalloc((void**)&counts, 3 * sizeof(unsigned)) != hipSuccess) {
     (void)hipFree(x);
     return RPK_ERR_NOMEM;
   }
   rpk_status st = RPK_OK;
-  unsigned h[2] = {0u, 0u};
+  unsigned h[3] = {0u, 0u, 0u};
   do {
-    if (hipMemsetAsync(counts, 0, 2 * sizeof(unsigned), s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    if (hipMemsetAsync(counts, 0, 3 * sizeof(unsigned), s) != hipSuccess) { st = RPK_ERR_HIP; break; }
     hipLaunchKernelGGL(k_fill_hash, dim3(1024), dim3(256), 0, s, x, (long long)A->n);
     const long long threads = (long long)A->nslices * 64;
     hipLaunchKernelGGL(k_cert_probe, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, csr_of(A), x, counts);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
-    A->cert = (h[1] > 0 && 8ull * h[0] <= h[1]) ? 1 : 0;
+    A->cert = (h[2] > 0 && 8ull * h[0] <= h[2]) ? 1 : (h[2] > 0 && 8ull * h[1] <= h[2]) ? 2 : 0;
   } while (0);
   (void)hipFree(x);
   (void)hipFree(counts);

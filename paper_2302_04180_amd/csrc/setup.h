@@ -97,11 +97,12 @@ __global__ void k_fill_sell(const int* rp, const int* ci, const double* v, int n
   }
 }
 
-// Probe at matrix creation: one wavefront per slice of at least kCertMinWidth
-// entries tries row_cert on x; counts[0] += slices where some row was not
-// certified, counts[1] += slices tried.  Rows whose sums often land exactly on a
-// rounding midpoint (many exact products) fail it, and there both paths would
-// run: the matrix then leaves it off.
+// Probe at matrix creation: one wavefront per slice tries row_cert on x, by
+// the bound alone and with the exactness check; counts[0] / counts[1] += slices
+// where some row was not certified that way, counts[2] += slices.  Rows whose
+// sums often land exactly on a rounding midpoint fail the first, and rows the
+// certificate cannot help fail both; the matrix takes the cheapest way that
+// rarely fails.
 __global__ void __launch_bounds__(256) k_cert_probe(Csr A, const double* __restrict__ x, unsigned* counts) {
   const int nslices = (A.n + 63) >> 6;
   const int s = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
@@ -109,14 +110,16 @@ __global__ void __launch_bounds__(256) k_cert_probe(Csr A, const double* __restr
   const int lane = threadIdx.x & 63;
   const long long off = A.sptr[s];
   const int w = (int)((A.sptr[s + 1] - off) >> 6);
-  if (w < kCertMinWidth) return;
   double y;
   const bool valid = (s << 6) + lane < A.n;
-  const bool cert = row_cert(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
-  const bool fail = __ballot(valid && !cert) != 0ull;
+  const bool c1 = row_cert<false>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
+  const bool fail1 = __ballot(valid && !c1) != 0ull;
+  const bool c2 = row_cert<true>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
+  const bool fail2 = __ballot(valid && !c2) != 0ull;
   if (lane == 0) {
-    atomicAdd(&counts[1], 1u);
-    if (fail) atomicAdd(&counts[0], 1u);
+    atomicAdd(&counts[2], 1u);
+    if (fail1) atomicAdd(&counts[0], 1u);
+    if (fail2) atomicAdd(&counts[1], 1u);
   }
 }
 

@@ -14,10 +14,12 @@ import pytest
 K_LO, K_HI = 2.0 ** -968, 2.0 ** 990
 
 
-def certify(a, x):
-    """(certified, y) by the kernel's steps for one row: terms a[j] * x[j]."""
+def certify(a, x, track=False):
+    """(certified, y) by the kernel's steps for one row: terms a[j] * x[j];
+    track: also accept a correction sum q that was accumulated exactly."""
     s = q = m = 0.0
     ok = True
+    exactq = True
     for aj, xj in zip(a, x):
         p = aj * xj
         ok &= (K_LO <= abs(p) < K_HI) or (p == 0.0 and (aj == 0.0 or xj == 0.0))
@@ -26,9 +28,18 @@ def certify(a, x):
         z = s1 - s
         t = (s - (s1 - z)) + (p - z)
         s = s1
-        q += t
-        q += e
+        if track:
+            for term in (t, e):
+                q1 = q + term
+                zq = q1 - q
+                exactq &= ((q - (q1 - zq)) + (term - zq)) == 0.0
+                q = q1
+        else:
+            q += t
+            q += e
         m += abs(t) + abs(e)
+    if track and ok and exactq:
+        return True, s + q
     k = 2.0 * len(a) + 2.0
     E = (m * (k * 2.0 ** -53)) * (1.0 + 2.0 ** -28) + k * 2.0 ** -1074
     y0 = s + q
@@ -82,13 +93,14 @@ def rows(rng, count):
             yield np.ldexp(rng.uniform(-1, 1, w), rng.integers(-1000, -900, w)), x
 
 
+@pytest.mark.parametrize("track", [False, True])
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_certified_rows_are_correctly_rounded(seed):
+def test_certified_rows_are_correctly_rounded(seed, track):
     rng = np.random.default_rng(seed)
     certified = 0
     total = 0
     for a, x in rows(rng, 1500):
-        ok, y = certify(list(map(float, a)), list(map(float, x)))
+        ok, y = certify(list(map(float, a)), list(map(float, x)), track)
         total += 1
         if ok:
             certified += 1
@@ -110,3 +122,6 @@ def test_midpoint_rows_are_declined():
     assert not ok or y == 1.0
     # all error terms zero: exact, certified even at zero
     assert certify([2.0, -2.0], [1.5, 1.5]) == (True, 0.0)
+    # with the exactness check the midpoint itself is settled: RN(1 + 2^-53) = 1
+    assert certify([1.0, 2.0 ** -53], [1.0, 1.0], track=True) == (True, 1.0)
+    assert certify([1.0 + 2.0 ** -52, 2.0 ** -53], [1.0, 1.0], track=True) == (True, 1.0 + 2.0 ** -51)
