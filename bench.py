@@ -31,8 +31,9 @@ MAXIT = 5000
 # `python3 bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; median per launch),
 # each scaled by what the same counter reads for the plain copy kernel of that
 # workload (512 MiB read + 512 MiB written).  Valid only while the kernel
-# sources still have the digest they had when the counters were taken.
-TRAFFIC = {"phase": 3, "kernel": "k_std_D<4>", "bytes": 229067507,
+# sources still have the digest they had when the counters were taken and the
+# solve runs the same FPE length.
+TRAFFIC = {"phase": 3, "kernel": "k_std_D<3>", "fpe": 3, "bytes": 229066350,
            "fetch_scale": 1.9999, "write_scale": 1.0000,
            "src_sha256": "8aed382732d32f9435899f4d4c72f17c919ae8d7aea1ab7bbd87b704ee4978f5"}
 
@@ -421,7 +422,8 @@ def main():
     dom_bytes = by["std_kernel"][dom]
     achieved = dom_bytes / avg_s / 1e9
     traffic = None
-    if TRAFFIC and TRAFFIC["src_sha256"] == kernel_digest() and TRAFFIC["phase"] == dom:
+    if (TRAFFIC and TRAFFIC["src_sha256"] == kernel_digest() and TRAFFIC["phase"] == dom
+            and TRAFFIC["fpe"] == tinfo["used"]["fpe"]):
         traffic = TRAFFIC["bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

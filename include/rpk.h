@@ -82,8 +82,8 @@ typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1, RPK_DOT_FPE = 2 } rpk_dotmo
 typedef struct {
   int32_t block;  /* workgroup size, a multiple of 64 in [64, 1024]; 0 = 512 */
   int32_t grid;   /* workgroups of the streaming kernels, >= 1; 0 = automatic */
-  int32_t fpe;    /* FPE length 1, 2, 4 or 8 (1 sends almost every term to the
-                     long accumulator); 0 = 4 */
+  int32_t fpe;    /* FPE length 1, 2, 3, 4 or 8 (1 sends almost every term to
+                     the long accumulator); 0 = 3 */
   int32_t graph;  /* solve: iterations per captured HIP graph launch; 0 = automatic,
                      -1 = no graph (direct launches) */
   int32_t tile;   /* batched solve: rows per tile, a multiple of 64 in [64, 2^20];

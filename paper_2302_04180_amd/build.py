@@ -13,9 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librpk.so")
-# kernel instantiations: 0 = plain FP64, 1/2/4/8 = exact with that FPE length,
+# kernel instantiations: 0 = plain FP64, 1/2/3/4/8 = exact with that FPE length,
 # 9 = lightweight FPE-8 dot products
-FPE_LENGTHS = (0, 1, 2, 4, 8, 9)
+FPE_LENGTHS = (0, 1, 2, 3, 4, 8, 9)
 
 # -ffp-contract=off: no a*b+c contraction anywhere (every fma is explicit);
 # packed FP32 instructions disabled; no fast-math.

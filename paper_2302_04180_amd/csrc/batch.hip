@@ -170,7 +170,7 @@ rpk_status check_opts(const rpk_opts* o) {
   if (o->maxit < 0 || !(o->tol >= 0.0) || o->xr_hist || o->resume) return RPK_ERR_ARG;
   const rpk_launch& l = o->launch;
   if (l.block && (l.block < 64 || l.block > 1024 || l.block % 64)) return RPK_ERR_ARG;
-  if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;
+  if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 3 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;
   if (l.graph < -1 || l.grid < 0 || l.grid > 65535) return RPK_ERR_ARG;
   if (l.tile && (l.tile < 64 || l.tile > (1 << 20) || l.tile % 64)) return RPK_ERR_ARG;
   return RPK_OK;
@@ -352,13 +352,13 @@ rpk_status autotune(const Ctx& c, BCfg* best) {
   struct Cand {
     int tile, block, fpe;
   };
-  const Cand all[] = {{1024, 256, 4}, {2048, 512, 4}, {4096, 512, 4}, {8192, 512, 4},
-                      {4096, 1024, 4}, {16384, 1024, 4}, {4096, 512, 2}, {2048, 256, 2}};
+  const Cand all[] = {{1024, 256, 3}, {2048, 512, 3}, {4096, 512, 3}, {8192, 512, 3},
+                      {4096, 1024, 3}, {16384, 1024, 3}, {4096, 512, 4}, {4096, 512, 2}};
   float best_ms = -1.f;
   for (const Cand& cd : all) {
     BCfg cfg{cd.tile, c.o->launch.block ? c.o->launch.block : cd.block,
              c.o->launch.fpe ? c.o->launch.fpe : cd.fpe, -1, c.o->launch.grid};
-    if (plain && cd.fpe != 4) continue;  // the FPE length does not exist in plain mode
+    if (plain && cd.fpe != 3) continue;  // the FPE length does not exist in plain mode
     if (cfg.tile < kTileMinAuto) continue;
     float ms = 0.f;
     RET_IF(trial_time(c, cfg, &ms));
@@ -538,7 +538,7 @@ rpk_status rpk_solve_batched(int32_t nsys, const rpk_matrix* const* A, const dou
   RET_IF(ensure_globals());
   BCfg cfg;
   if (tile) {
-    cfg = BCfg{tile, o->launch.block ? o->launch.block : 512, o->launch.fpe ? o->launch.fpe : 4, o->launch.graph,
+    cfg = BCfg{tile, o->launch.block ? o->launch.block : 512, o->launch.fpe ? o->launch.fpe : 3, o->launch.graph,
                o->launch.grid};
   } else {
     RET_IF(autotune(c, &cfg));

@@ -46,6 +46,7 @@ rpk_status by_fpe(int N, Args&&... args) {
     case 0: return F<0>::call(args...);
     case 1: return F<1>::call(args...);
     case 2: return F<2>::call(args...);
+    case 3: return F<3>::call(args...);
     case 4: return F<4>::call(args...);
     case 8: return F<8>::call(args...);
   }

@@ -39,12 +39,14 @@ struct KernB {
 extern template struct Kern<0>;
 extern template struct Kern<1>;
 extern template struct Kern<2>;
+extern template struct Kern<3>;
 extern template struct Kern<4>;
 extern template struct Kern<8>;
 extern template struct Kern<LW8>;  // lightweight dots: single solves and rpk_fpedot only
 extern template struct KernB<0>;
 extern template struct KernB<1>;
 extern template struct KernB<2>;
+extern template struct KernB<3>;
 extern template struct KernB<4>;
 extern template struct KernB<8>;
 

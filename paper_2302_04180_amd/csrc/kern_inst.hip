@@ -1,5 +1,5 @@
 // kern_inst.hip -- launchers of Kern<RPK_N>; compiled once per FPE length
-// (RPK_N = 0 plain FP64, 1, 2, 4, 8 exact, 9 = LW8 lightweight) so the
+// (RPK_N = 0 plain FP64, 1, 2, 3, 4, 8 exact, 9 = LW8 lightweight) so the
 // instantiations build in parallel.
 #include "kern.h"
 

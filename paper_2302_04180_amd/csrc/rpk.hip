@@ -28,10 +28,10 @@ struct Cfg {
 
 rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
   c->block = (L && L->block) ? L->block : 512;
-  c->fpe = (L && L->fpe) ? L->fpe : 4;
+  c->fpe = (L && L->fpe) ? L->fpe : 3;
   c->graph = L ? L->graph : 0;
   if (c->block < 64 || c->block > 1024 || (c->block % 64) != 0) return RPK_ERR_ARG;
-  if (c->fpe != 1 && c->fpe != 2 && c->fpe != 4 && c->fpe != 8) return RPK_ERR_ARG;
+  if (c->fpe != 1 && c->fpe != 2 && c->fpe != 3 && c->fpe != 4 && c->fpe != 8) return RPK_ERR_ARG;
   if (c->graph < -1) return RPK_ERR_ARG;
   if (L && L->grid) {
     if (L->grid < 1 || L->grid > 65535) return RPK_ERR_ARG;

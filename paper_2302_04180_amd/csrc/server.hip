@@ -373,14 +373,14 @@ rpk_status rpk_server_create(const rpk_server_opts* o, rpk_server** out) {
   if (so.maxit < 0 || !(so.tol >= 0.0) || so.hist || so.xr_hist || so.timing || so.resume) return RPK_ERR_ARG;
   const rpk_launch& l = so.launch;
   if (l.block && (l.block < 64 || l.block > 1024 || l.block % 64)) return RPK_ERR_ARG;
-  if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;
+  if (l.fpe && l.fpe != 1 && l.fpe != 2 && l.fpe != 3 && l.fpe != 4 && l.fpe != 8) return RPK_ERR_ARG;
   if (l.tile && (l.tile < 64 || l.tile > (1 << 20) || l.tile % 64)) return RPK_ERR_ARG;
   rpk_server* S = new (std::nothrow) rpk_server();
   if (!S) return RPK_ERR_NOMEM;
   S->o = *o;
   S->block = l.block ? l.block : 512;
   S->tile = l.tile ? l.tile : 4096;
-  S->N = (so.dots == RPK_DOT_PLAIN) ? 0 : (l.fpe ? l.fpe : 4);
+  S->N = (so.dots == RPK_DOT_PLAIN) ? 0 : (l.fpe ? l.fpe : 3);
   S->nvec = nvec_of(so.variant);
   S->nph = (so.variant == RPK_STD) ? 5 : (so.variant == RPK_PCG) ? 3 : 4;
   rpk_status st = RPK_OK;

@@ -18,7 +18,7 @@ def gdot(x, y, **kw):
     return float(H(rpk.exdot(T(x), T(y), **kw)))
 
 
-@pytest.mark.parametrize("fpe", [1, 2, 4, 8])
+@pytest.mark.parametrize("fpe", [1, 2, 3, 4, 8])
 def test_closed_forms(fpe):
     for label, x, y, expected in CASES:
         say("closed form", label, "fpe", fpe)
@@ -40,7 +40,7 @@ def test_launch_shape_and_fpe_sweep(orc):
     x, y = _random_vectors(rng, 300001, "extreme")
     ref = orc.exdot(x, y)
     xt, yt = T(x), T(y)
-    for fpe in (1, 2, 4, 8):
+    for fpe in (1, 2, 3, 4, 8):
         for block in (64, 128, 256, 512, 1024):
             for grid in (1, 3, 8, 64, 1000):
                 got = float(H(rpk.exdot(xt, yt, block=block, grid=grid, fpe=fpe)))

@@ -67,7 +67,7 @@ def test_spmv_vs_oracle(orc, name, A):
     for kind in ("uniform", "wide", "extreme"):
         x = xvec(rng, n, kind)
         ref = orc.exspmv(*A, x)
-        for fpe in (1, 2, 4, 8):
+        for fpe in (1, 2, 3, 4, 8):
             say("spmv", name, kind, "fpe", fpe)
             got = H(rpk.exspmv(M, T(x), fpe=fpe))
             assert same(got, ref), (name, kind, fpe, first_diff(got, ref))
