@@ -21,6 +21,7 @@ struct rpk_matrix {
   long long* sptr = nullptr;
   int* scol = nullptr;
   double* sval = nullptr;
+  long long sell_entries = 0;      // entries of the SELL copy, padding included
   int cert = 0;                    // rows of wide slices try the certified sum (see Csr)
 };
 
@@ -36,9 +37,26 @@ using namespace rpk;
 constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert}; }
+inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert, 0}; }
 
 inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK_PCG ? 4 : 16; }
+
+// MI355X's Infinity Cache: 256 MiB in front of HBM, shared by all XCDs.
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
+
+// Leading SELL slices of A that a solve reads with ordinary loads (Csr::keep):
+// as much of the matrix as fits in nine tenths of the Infinity Cache next to
+// the vectors one iteration touches (the variant's work vectors, x and the
+// Jacobi vector), so that the next SpMV finds it there.  Slices are counted
+// in proportion to the SELL entries.
+inline int keep_slices(const rpk_matrix* A, int variant) {
+  const double vecs = (double)(nvec_of(variant) + 2) * (double)A->n * 8.0;
+  const double room = 0.9 * kInfinityCacheBytes - vecs;
+  const double sell = (double)A->sell_entries * 12.0;
+  if (room <= 0.0 || sell <= 0.0) return 0;
+  if (room >= sell) return A->nslices;
+  return (int)((double)A->nslices * (room / sell));
+}
 
 template <template <int> class F, typename... Args>
 rpk_status by_fpe(int N, Args&&... args) {

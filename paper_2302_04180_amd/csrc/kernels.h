@@ -54,6 +54,10 @@ struct Csr {
   // 2 = also accepting an exactly accumulated correction (decided once per
   // matrix at creation by a probe; every path gives the same bits)
   int cert;
+  // slices [0, keep) read their entries with ordinary loads, which leave them
+  // in the Infinity Cache for the next SpMV; the rest with non-temporal loads,
+  // which leave the cache to the vectors (the same values either way)
+  int keep;
 };
 
 // Device-resident solver state (one per solve, in the caller's workspace).
@@ -258,10 +262,17 @@ struct GatherX {  // plain vector
   __device__ __forceinline__ double operator()(int c) const { return x[c]; }
 };
 
+// A matrix entry or column index: non-temporal (NT) or ordinary load.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_entry(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // Exact fast path of one row in one lane: FPE of the twoprod terms of entries
 // j = 0..w-1 (stride 64 in the slice).  Sets `bad` when the FPE overflows or a
 // product needs the integer path.
-template <int N, class Gth>
+template <int N, bool NT, class Gth>
 __device__ __forceinline__ double row_fast(const double* __restrict__ sval, const int* __restrict__ scol,
                                            const Gth& gx, int w, bool& bad) {
   Fpe<N> f;
@@ -275,8 +286,8 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const bool in = j0 + u < w;
-      a[u] = in ? __builtin_nontemporal_load(sval + (size_t)(j0 + u) * 64) : 0.0;
-      c[u] = in ? __builtin_nontemporal_load(scol + (size_t)(j0 + u) * 64) : -1;
+      a[u] = in ? ld_entry<NT>(sval + (size_t)(j0 + u) * 64) : 0.0;
+      c[u] = in ? ld_entry<NT>(scol + (size_t)(j0 + u) * 64) : -1;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
@@ -310,7 +321,7 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
 // path -- when neither shows it, or for a product out of range or a sum that
 // is non-finite or, for the bound, zero, tiny or huge.  When it returns true, y
 // is the correctly rounded row sum: the same bits as the FPE path.
-template <bool Track, class Gth>
+template <bool Track, bool NT, class Gth>
 __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const int* __restrict__ scol, const Gth& gx,
                                          int w, double& y) {
   double s = 0.0, q = 0.0, m = 0.0;
@@ -321,8 +332,8 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const bool in = j0 + u < w;
-      a[u] = in ? __builtin_nontemporal_load(sval + (size_t)(j0 + u) * 64) : 0.0;
-      c[u] = in ? __builtin_nontemporal_load(scol + (size_t)(j0 + u) * 64) : -1;
+      a[u] = in ? ld_entry<NT>(sval + (size_t)(j0 + u) * 64) : 0.0;
+      c[u] = in ? ld_entry<NT>(scol + (size_t)(j0 + u) * 64) : -1;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
@@ -403,8 +414,8 @@ __device__ inline double row_slow(const double* sv, const int* sc, const Gth& gx
 
 // Row values of the 64 rows of one wavefront (rows first..first+63, first a
 // multiple of 64, lane l holds row first+l); must be called by all 64 lanes.
-template <int N, class Gth>
-__device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int row, bool valid, long long* wsa_block) {
+template <int N, bool NT, class Gth>
+__device__ __forceinline__ double rows_wave_nt(const Csr& A, const Gth& gx, int row, bool valid, long long* wsa_block) {
   if (__ballot(valid) == 0ull) return 0.0;
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(row) >> 6;
@@ -420,8 +431,8 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const bool in = j0 + u < w;
-        a[u] = in ? __builtin_nontemporal_load(sv + (size_t)(j0 + u) * 64) : 0.0;
-        c[u] = in ? __builtin_nontemporal_load(sc + (size_t)(j0 + u) * 64) : -1;
+        a[u] = in ? ld_entry<NT>(sv + (size_t)(j0 + u) * 64) : 0.0;
+        c[u] = in ? ld_entry<NT>(sc + (size_t)(j0 + u) * 64) : -1;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
@@ -436,11 +447,11 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     // it: its dependency chain is a few additions per entry, an FPE
     // insertion's several twosums with a data-dependent exit after each
     if (A.cert) {
-      const bool cert = (A.cert == 2) ? row_cert<true>(sv, sc, gx, w, y) : row_cert<false>(sv, sc, gx, w, y);
+      const bool cert = (A.cert == 2) ? row_cert<true, NT>(sv, sc, gx, w, y) : row_cert<false, NT>(sv, sc, gx, w, y);
       if (__ballot(valid && !cert) == 0ull) return y;
     }
     bool bad = false;
-    y = row_fast<kRowN<N>>(sv, sc, gx, w, bad);
+    y = row_fast<kRowN<N>, NT>(sv, sc, gx, w, bad);
     bad = bad && valid;
     unsigned long long m = __ballot(bad);
     if (m) {
@@ -454,6 +465,12 @@ __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int r
     }
     return y;
   }
+}
+
+template <int N, class Gth>
+__device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int row, bool valid, long long* wsa_block) {
+  if ((__builtin_amdgcn_readfirstlane(row) >> 6) < A.keep) return rows_wave_nt<N, false>(A, gx, row, valid, wsa_block);
+  return rows_wave_nt<N, true>(A, gx, row, valid, wsa_block);
 }
 
 template <int N>

@@ -232,6 +232,7 @@ static rpk_status build_sell(rpk_matrix* A, hipStream_t s) {
     if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
     if (hipMemcpyAsync(&total, A->sptr + ns, sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    A->sell_entries = total;
     const size_t cnt = (size_t)(total > 0 ? total : 1);
     if (hipMalloc((void**)&A->scol, cnt * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&A->sval, cnt * sizeof(double)) != hipSuccess) { st = RPK_ERR_NOMEM; break; }
@@ -457,6 +458,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
+  Ac.keep = keep_slices(A, variant);
 
   const bool resume = o->resume != 0;
   // reduction scratch to zero; caller-visible histories to zero (not when resuming)

@@ -112,9 +112,9 @@ __global__ void __launch_bounds__(256) k_cert_probe(Csr A, const double* __restr
   const int w = (int)((A.sptr[s + 1] - off) >> 6);
   double y;
   const bool valid = (s << 6) + lane < A.n;
-  const bool c1 = row_cert<false>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
+  const bool c1 = row_cert<false, true>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
   const bool fail1 = __ballot(valid && !c1) != 0ull;
-  const bool c2 = row_cert<true>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
+  const bool c2 = row_cert<true, true>(A.sval + off + lane, A.scol + off + lane, GatherX{x}, w, y);
   const bool fail2 = __ballot(valid && !c2) != 0ull;
   if (lane == 0) {
     atomicAdd(&counts[2], 1u);
