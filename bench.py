@@ -9,6 +9,8 @@ dominant kernel), and the exact CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --profile   (fixed short workload for rocprofv3 counter passes)
+       python bench.py --profile-spmv   (lone SpMVs of the 27-point 159^3 and 7-point 128^3
+                                         matrices, for the same counter passes)
 """
 import argparse
 import hashlib
@@ -126,6 +128,34 @@ def profile_workload():
     torch.cuda.synchronize()
     M.close()
     print("profile workload done", flush=True)
+
+
+def profile_spmv_workload():
+    """Lone exact and plain SpMVs (three of each) of the 27-point e-type and
+    symmetric 27-point 159^3 matrices and the 7-point 128^3 one, after the same
+    copy kernel of known size."""
+    import torch
+
+    from paper_2302_04180_amd import inputs, rpk
+    torch.cuda.set_device(0)
+    src = torch.rand(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)  # reads 512 MiB, writes 512 MiB
+    torch.cuda.synchronize()
+    del src, dst
+    for gen, edge in ((inputs.poisson27_etype, 159), (inputs.poisson27, 159), (inputs.poisson7, N_EDGE)):
+        A = gen(edge)
+        M = rpk.Matrix(*A)
+        del A
+        x = torch.rand(M.n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+        for dots in (rpk.EXACT, rpk.PLAIN):
+            for _ in range(3):
+                rpk.exspmv(M, x, dots=dots)
+        torch.cuda.synchronize()
+        print("%s %d: n %d nnz %d" % (gen.__name__, edge, M.n, M.nnz), flush=True)
+        M.close()
+    print("profile spmv workload done", flush=True)
 
 
 def batched_leg(torch, rpk, inputs, reps=3):
@@ -337,6 +367,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile", action="store_true", help="run the fixed counter-collection workload only")
+    ap.add_argument("--profile-spmv", action="store_true", help="run the lone-SpMV counter-collection workload only")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched, serving and e-type legs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -345,6 +376,8 @@ def main():
         sys.exit(2)
     if args.profile:
         return profile_workload()
+    if args.profile_spmv:
+        return profile_spmv_workload()
 
     import numpy as np
     import torch
