@@ -44,13 +44,13 @@ inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK
 // MI355X's Infinity Cache: 256 MiB in front of HBM, shared by all XCDs.
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
-// Leading SELL slices of A that a solve reads with ordinary loads (Csr::keep):
-// as much of the matrix as fits in nine tenths of the Infinity Cache next to
-// the vectors one iteration touches (the variant's work vectors, x and the
-// Jacobi vector), so that the next SpMV finds it there.  Slices are counted
-// in proportion to the SELL entries.
-inline int keep_slices(const rpk_matrix* A, int variant) {
-  const double vecs = (double)(nvec_of(variant) + 2) * (double)A->n * 8.0;
+// Leading SELL slices of A read with ordinary loads (Csr::keep): as much of
+// the matrix as fits in nine tenths of the Infinity Cache next to `nvec`
+// n-vectors (those one solver iteration touches, or x and y of a lone SpMV),
+// so that the next SpMV finds it there.  Slices are counted in proportion to
+// the SELL entries.
+inline int keep_slices(const rpk_matrix* A, int nvec) {
+  const double vecs = (double)nvec * (double)A->n * 8.0;
   const double room = 0.9 * kInfinityCacheBytes - vecs;
   const double sell = (double)A->sell_entries * 12.0;
   if (room <= 0.0 || sell <= 0.0) return 0;

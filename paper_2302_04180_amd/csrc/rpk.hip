@@ -396,7 +396,9 @@ rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t d
   Cfg c;
   RET_IF(resolve(launch_cfg, A->n, &c));
   const int N = (dots == RPK_DOT_PLAIN) ? 0 : c.fpe;  // the lightweight mode keeps the exact rows
-  return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, csr_of(A), x, y);
+  Csr Ac = csr_of(A);
+  Ac.keep = keep_slices(A, 2);  // repeated SpMVs of a matrix that fits reuse it from the cache
+  return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, Ac, x, y);
 }
 
 rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* o, size_t* bytes) {
@@ -458,7 +460,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
-  Ac.keep = keep_slices(A, variant);
+  Ac.keep = keep_slices(A, nvec_of(variant) + 2);  // + x and the Jacobi vector
 
   const bool resume = o->resume != 0;
   // reduction scratch to zero; caller-visible histories to zero (not when resuming)
