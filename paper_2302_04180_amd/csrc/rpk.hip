@@ -460,7 +460,9 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
-  Ac.keep = keep_slices(A, nvec_of(variant) + 2);  // + x and the Jacobi vector
+  // what one iteration keeps in the Infinity Cache: the work vectors, x and the
+  // Jacobi vector; the pipelined loop streams six of its 18 past it (ld_far)
+  Ac.keep = keep_slices(A, variant == RPK_PIPELINED ? 11 : nvec_of(variant) + 2);
 
   const bool resume = o->resume != 0;
   // reduction scratch to zero; caller-visible histories to zero (not when resuming)

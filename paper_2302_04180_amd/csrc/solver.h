@@ -545,6 +545,14 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
 }
 
 // P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
+// The pipelined loop's vectors that are next read a whole iteration later (s, s^,
+// z, x) or never written (r0, the Jacobi vector) go through non-temporal loads
+// and stores: the Infinity Cache is then left to the eleven vectors that the
+// next kernel or two read back, and to the part of the matrix that fits beside
+// them (the same values either way).
+__device__ __forceinline__ double ld_far(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_far(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 template <int N, bool Defer = false>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
@@ -554,22 +562,23 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
 #pragma unroll
   for (int j = 0; j < 4; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i], r0 = V.r0[i];
-    const double ph = fma(beta, fma(-omega, V.sh[i], V.ph[i]), rh);  // S1
-    const double sv = fma(beta, fma(-omega, V.z[i], V.s[i]), w);      // S2
-    const double sh = fma(beta, fma(-omega, V.zh[i], V.sh[i]), wh);  // S3
-    const double z = fma(beta, fma(-omega, V.v[i], V.z[i]), V.t[i]);  // S4
-    const double q = fma(-alpha, sv, V.r[i]);                         // S5
-    const double qh = fma(-alpha, sh, rh);                            // S6
-    const double y = fma(-alpha, z, w);                               // S7
+    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i], r0 = ld_far(&V.r0[i]);
+    const double sh_old = ld_far(&V.sh[i]), z_old = ld_far(&V.z[i]);
+    const double ph = fma(beta, fma(-omega, sh_old, V.ph[i]), rh);      // S1
+    const double sv = fma(beta, fma(-omega, z_old, ld_far(&V.s[i])), w);  // S2
+    const double sh = fma(beta, fma(-omega, V.zh[i], sh_old), wh);      // S3
+    const double z = fma(beta, fma(-omega, V.v[i], z_old), V.t[i]);     // S4
+    const double q = fma(-alpha, sv, V.r[i]);                           // S5
+    const double qh = fma(-alpha, sh, rh);                              // S6
+    const double y = fma(-alpha, z, w);                                 // S7
     V.ph[i] = ph;
-    V.s[i] = sv;
-    V.sh[i] = sh;
-    V.z[i] = z;
+    st_far(&V.s[i], sv);
+    st_far(&V.sh[i], sh);
+    st_far(&V.z[i], z);
     V.q[i] = q;
     V.qh[i] = qh;
     V.y[i] = y;
-    V.zh[i] = A.dinv[i] * z;                                          // S9
+    V.zh[i] = ld_far(&A.dinv[i]) * z;                                   // S9
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
     d[2].add(r0, sv, s.sa + 2 * SA_D, &s.flag[2]);                    // S16: <r0,s>
@@ -589,16 +598,16 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
 #pragma unroll
   for (int j = 0; j < 3; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double qh = V.qh[i], y = V.y[i], r0 = V.r0[i];
-    const double x = fma(omega, qh, fma(alpha, V.ph[i], V.x[i]));      // S12
-    const double r = fma(-omega, y, V.q[i]);                           // S13
-    const double rh = fma(-omega, fma(-alpha, V.zh[i], V.wh[i]), qh);  // S14
-    const double w = fma(-omega, fma(-alpha, V.v[i], V.t[i]), y);      // S15
-    V.x[i] = x;
+    const double qh = V.qh[i], y = V.y[i], r0 = ld_far(&V.r0[i]);
+    const double x = fma(omega, qh, fma(alpha, V.ph[i], ld_far(&V.x[i])));  // S12
+    const double r = fma(-omega, y, V.q[i]);                               // S13
+    const double rh = fma(-omega, fma(-alpha, V.zh[i], V.wh[i]), qh);      // S14
+    const double w = fma(-omega, fma(-alpha, V.v[i], V.t[i]), y);          // S15
+    st_far(&V.x[i], x);
     V.r[i] = r;
     V.rh[i] = rh;
     V.w[i] = w;
-    V.wh[i] = A.dinv[i] * w;                                           // S17
+    V.wh[i] = ld_far(&A.dinv[i]) * w;                                      // S17
     record_xr(V, iter, A.n, i, x, r);
     d[0].add(r0, r, s.sa, &s.flag[0]);                                 // S16
     d[1].add(r0, w, s.sa + SA_D, &s.flag[1]);
