@@ -38,7 +38,7 @@ MAXIT = 5000
 # solve runs the same FPE length.
 TRAFFIC = {"phase": 3, "kernel": "k_std_D<3>", "fpe": 3, "bytes": 229567677,
            "fetch_scale": 1.9999, "write_scale": 1.0000,
-           "src_sha256": "4db789978eea33778a4c76244ba3a8805aa5119d75414b820e13cda3c7dacedd"}
+           "src_sha256": "5f4d3098648be17454d1e1b88e1a1e3938c68fcd5712ac23d864313987fc35c7"}
 
 
 KERNEL_SOURCES = ("device.h", "kernels.h", "solver.h")

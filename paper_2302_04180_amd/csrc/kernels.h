@@ -467,6 +467,8 @@ __device__ __forceinline__ double rows_wave_nt(const Csr& A, const Gth& gx, int 
   }
 }
 
+// The wavefront's slice decides the kind of matrix load (Csr::keep); the values
+// and so the results are the same either way.
 template <int N, class Gth>
 __device__ __forceinline__ double rows_wave_g(const Csr& A, const Gth& gx, int row, bool valid, long long* wsa_block) {
   if ((__builtin_amdgcn_readfirstlane(row) >> 6) < A.keep) return rows_wave_nt<N, false>(A, gx, row, valid, wsa_block);
