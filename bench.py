@@ -36,9 +36,9 @@ MAXIT = 5000
 # workload (512 MiB read + 512 MiB written).  Valid only while the kernel
 # sources still have the digest they had when the counters were taken and the
 # solve runs the same FPE length.
-TRAFFIC = {"phase": 3, "kernel": "k_std_D<3>", "fpe": 3, "bytes": 229567677,
+TRAFFIC = {"phase": 3, "kernel": "k_std_D<3>", "fpe": 3, "bytes": 229561907,
            "fetch_scale": 1.9999, "write_scale": 1.0000,
-           "src_sha256": "5f4d3098648be17454d1e1b88e1a1e3938c68fcd5712ac23d864313987fc35c7"}
+           "src_sha256": "9dc3611905f8eed1287412358b85b5917fd257d23283af2380ed89b77a7c1698"}
 
 
 KERNEL_SOURCES = ("device.h", "kernels.h", "solver.h")

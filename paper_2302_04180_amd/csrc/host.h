@@ -58,6 +58,12 @@ inline int keep_slices(const rpk_matrix* A, int nvec) {
   return (int)((double)A->nslices * (room / sell));
 }
 
+// Whether the standard loop streams its far vectors (Vecs::far): when its ten
+// vectors do not fit in nine tenths of the Infinity Cache.
+inline bool std_streams_far(const rpk_matrix* A) {
+  return (double)(nvec_of(RPK_STD) + 2) * (double)A->n * 8.0 > 0.9 * kInfinityCacheBytes;
+}
+
 template <template <int> class F, typename... Args>
 rpk_status by_fpe(int N, Args&&... args) {
   switch (N) {

@@ -39,12 +39,15 @@ rpk_status Kern<N>::resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
 template <int N>
 rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
   if (variant == RPK_STD) {
+    const bool far = V.far != 0;  // x, p, r0 and the Jacobi vector streamed past the Infinity Cache
     switch (ph) {
-      case 0: return launch(k_std_A<N>, G, B, 0, s, A, V);
+      case 0: return far ? launch(k_std_A<N, true>, G, B, 0, s, A, V) : launch(k_std_A<N, false>, G, B, 0, s, A, V);
       case 1: return launch(k_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 2: return launch(k_std_C<N>, G, B, 0, s, A, V);
+      case 2: return far ? launch(k_std_C<N, true>, G, B, 0, s, A, V) : launch(k_std_C<N, false>, G, B, 0, s, A, V);
       case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
-      default: return launch(k_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      default:
+        return far ? launch(k_std_E<N, true>, G, B, shm_bytes(N, 2, false, B), s, A, V, red)
+                   : launch(k_std_E<N, false>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
     }
   }
   if (variant == RPK_PCG) {

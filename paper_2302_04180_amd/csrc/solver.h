@@ -39,6 +39,8 @@ struct Vecs {
   State* st;
   double* hist;  // [maxit][HIST_W] or null
   double* xr;    // [maxit][2][n] or null
+  int far;       // standard loop: x, p, r0 and the Jacobi vector are streamed (the
+                 // host then launches the Far instantiations of kernels A, C, E)
 };
 
 __device__ __forceinline__ double* hist_row(const Vecs& V, int iter) {
@@ -340,7 +342,29 @@ __device__ __forceinline__ void std_init_body(const Csr& A, const Vecs& V, const
   publish_step<N, 1, FIN_ENTRY>(d, s, V, red, rec);
 }
 
+// Vectors that are next read a whole iteration after they are written, or
+// never written, go through non-temporal loads and stores where the loop's
+// vectors do not all fit in the Infinity Cache: the cache is then left to the
+// vectors that the next kernel or two read back, and to the part of the matrix
+// that fits beside them (the same values either way).  The pipelined loop
+// always streams s, s^, z, x, r0 and the Jacobi vector (its 18 vectors never
+// fit); the standard loop streams x, p, r0 and the Jacobi vector when its ten
+// do not (Vecs::far).
+template <bool Far>
+__device__ __forceinline__ double ld_v(const double* p) {
+  if constexpr (Far) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool Far>
+__device__ __forceinline__ void st_v(double* p, double v) {
+  if constexpr (Far) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+__device__ __forceinline__ double ld_far(const double* p) { return ld_v<true>(p); }
+__device__ __forceinline__ void st_far(double* p, double v) { st_v<true>(p, v); }
+
 // A: S12 (iterations after the first) and S1
+template <bool Far = false>
 __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R) {
   const State* st = V.st;
   const bool upd = st->iter > 0;
@@ -350,10 +374,10 @@ __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R)
     const bool two = i1 < R.hi;
     const int j1 = two ? i1 : i0;
     double p[2], s[2], r[2], d[2];
-    p[0] = V.p[i0];
-    p[1] = V.p[j1];
-    d[0] = A.dinv[i0];
-    d[1] = A.dinv[j1];
+    p[0] = ld_v<Far>(&V.p[i0]);
+    p[1] = ld_v<Far>(&V.p[j1]);
+    d[0] = ld_v<Far>(&A.dinv[i0]);
+    d[1] = ld_v<Far>(&A.dinv[j1]);
     if (upd) {
       s[0] = V.s[i0];
       s[1] = V.s[j1];
@@ -367,7 +391,7 @@ __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R)
       double pv = p[u];
       if (upd) {
         pv = fma(beta, fma(-omega, s[u], pv), r[u]);  // S12
-        V.p[i] = pv;
+        st_v<Far>(&V.p[i], pv);
       }
       V.ph[i] = d[u] * pv;  // S1
     }
@@ -394,6 +418,7 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
 }
 
 // C: S4 + S5
+template <bool Far = false>
 __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R) {
   const double alpha = V.st->alpha;
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
@@ -401,7 +426,7 @@ __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R)
     const bool two = i1 < R.hi;
     const int j1 = two ? i1 : i0;
     const double s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
-    const double d0 = A.dinv[i0], d1 = A.dinv[j1];
+    const double d0 = ld_v<Far>(&A.dinv[i0]), d1 = ld_v<Far>(&A.dinv[j1]);
     const double q0 = fma(-alpha, s0, r0);  // S4
     V.q[i0] = q0;
     V.qh[i0] = d0 * q0;                     // S5
@@ -435,7 +460,7 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
 }
 
 // E: S8 + S9 + S10/S11 partials
-template <int N>
+template <int N, bool Far = false>
 __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s) {
   const State* st = V.st;
@@ -454,10 +479,10 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
       const int i = u ? (two ? i1 : i0) : i0;
       qh[u] = V.qh[i];
       ph[u] = V.ph[i];
-      xo[u] = V.x[i];
+      xo[u] = ld_v<Far>(&V.x[i]);
       y[u] = V.y[i];
       q[u] = V.q[i];
-      r0[u] = V.r0[i];
+      r0[u] = ld_v<Far>(&V.r0[i]);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -465,7 +490,7 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
       const int i = u ? i1 : i0;
       const double x = fma(omega, qh[u], fma(alpha, ph[u], xo[u]));  // S8
       const double r = fma(-omega, y[u], q[u]);                       // S9
-      V.x[i] = x;
+      st_v<Far>(&V.x[i], x);
       V.r[i] = r;
       record_xr(V, iter, A.n, i, x, r);
       d[0].add(r0[u], r, s.sa, &s.flag[0]);                           // S10
@@ -545,14 +570,6 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
 }
 
 // P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
-// The pipelined loop's vectors that are next read a whole iteration later (s, s^,
-// z, x) or never written (r0, the Jacobi vector) go through non-temporal loads
-// and stores: the Infinity Cache is then left to the eleven vectors that the
-// next kernel or two read back, and to the part of the matrix that fits beside
-// them (the same values either way).
-__device__ __forceinline__ double ld_far(const double* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void st_far(double* p, double v) { __builtin_nontemporal_store(v, p); }
-
 template <int N, bool Defer = false>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
@@ -708,10 +725,10 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
   std_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
   if (V.st->done) return;
-  std_A_body(A, V, my_rows(A.n));
+  std_A_body<Far>(A, V, my_rows(A.n));
 }
 
 template <int N>
@@ -723,10 +740,10 @@ __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
   std_B_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
   if (V.st->done) return;
-  std_C_body(A, V, my_rows(A.n));
+  std_C_body<Far>(A, V, my_rows(A.n));
 }
 
 template <int N>
@@ -738,13 +755,13 @@ __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
   std_D_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   shm_init(s, 2);
-  std_E_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_E_body<N, Far>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N>
