@@ -58,10 +58,21 @@ inline int keep_slices(const rpk_matrix* A, int nvec) {
   return (int)((double)A->nslices * (room / sell));
 }
 
-// Whether the standard loop streams its far vectors (Vecs::far): when its ten
-// vectors do not fit in nine tenths of the Infinity Cache.
-inline bool std_streams_far(const rpk_matrix* A) {
-  return (double)(nvec_of(RPK_STD) + 2) * (double)A->n * 8.0 > 0.9 * kInfinityCacheBytes;
+// Whether a solve streams vectors past the Infinity Cache beyond what it always
+// does (Vecs::far): the standard loop when its ten vectors do not fit in nine
+// tenths of the cache, the pipelined loop when the eleven it otherwise keeps
+// do not.
+inline bool streams_far(const rpk_matrix* A, int variant) {
+  const int kept = variant == RPK_STD ? nvec_of(RPK_STD) + 2 : variant == RPK_PIPELINED ? 11 : 0;
+  return kept > 0 && (double)kept * (double)A->n * 8.0 > 0.9 * kInfinityCacheBytes;
+}
+
+// Vectors of one iteration that stay in the Infinity Cache (the work vectors,
+// x and the Jacobi vector, less those streamed past it)
+inline int cached_vectors(int variant, bool far) {
+  if (variant == RPK_PIPELINED) return far ? 4 : 11;
+  if (variant == RPK_STD) return far ? 6 : nvec_of(RPK_STD) + 2;
+  return nvec_of(variant) + 2;
 }
 
 template <template <int> class F, typename... Args>

@@ -61,9 +61,13 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
   // when the grid has a single one
   const int Gs = G < 2 ? 2 : G;
   switch (ph) {
-    case 0: return launch(k_pipe_P1<N>, G, B, shm_bytes(N, 4, false, B), s, A, V, red);
+    case 0:
+      return V.far ? launch(k_pipe_P1<N, true>, G, B, shm_bytes(N, 4, false, B), s, A, V, red)
+                   : launch(k_pipe_P1<N, false>, G, B, shm_bytes(N, 4, false, B), s, A, V, red);
     case 1: return launch(k_pipe_spmv_fin<N, 1, 4, FIN_POMEGA>, Gs, B, shm_bytes(N, 4, true, B), s, A, V, red);
-    case 2: return launch(k_pipe_P3<N>, G, B, shm_bytes(N, 3, false, B), s, A, V, red);
+    case 2:
+      return V.far ? launch(k_pipe_P3<N, true>, G, B, shm_bytes(N, 3, false, B), s, A, V, red)
+                   : launch(k_pipe_P3<N, false>, G, B, shm_bytes(N, 3, false, B), s, A, V, red);
     default: return launch(k_pipe_spmv_fin<N, 0, 3, FIN_S19>, Gs, B, shm_bytes(N, 3, true, B), s, A, V, red);
   }
 }

@@ -460,11 +460,8 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Red red = make_red(w, l, G);
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
-  // what one iteration keeps in the Infinity Cache: the work vectors, x and the
-  // Jacobi vector, less those streamed past it (ld_v): six of the pipelined
-  // loop's 18, four of the standard loop's ten when the ten do not fit
-  V.far = (variant == RPK_STD && std_streams_far(A)) ? 1 : 0;
-  Ac.keep = keep_slices(A, variant == RPK_PIPELINED ? 11 : V.far ? 6 : nvec_of(variant) + 2);
+  V.far = streams_far(A, variant) ? 1 : 0;
+  Ac.keep = keep_slices(A, cached_vectors(variant, V.far != 0));
 
   const bool resume = o->resume != 0;
   // reduction scratch to zero; caller-visible histories to zero (not when resuming)

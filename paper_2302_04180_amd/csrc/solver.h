@@ -39,8 +39,9 @@ struct Vecs {
   State* st;
   double* hist;  // [maxit][HIST_W] or null
   double* xr;    // [maxit][2][n] or null
-  int far;       // standard loop: x, p, r0 and the Jacobi vector are streamed (the
-                 // host then launches the Far instantiations of kernels A, C, E)
+  int far;       // vectors that do not fit are streamed (ld_v): set by the host, which
+                 // then launches the Far / Mid instantiations of the standard /
+                 // pipelined kernels
 };
 
 __device__ __forceinline__ double* hist_row(const Vecs& V, int iter) {
@@ -348,8 +349,11 @@ __device__ __forceinline__ void std_init_body(const Csr& A, const Vecs& V, const
 // vectors that the next kernel or two read back, and to the part of the matrix
 // that fits beside them (the same values either way).  The pipelined loop
 // always streams s, s^, z, x, r0 and the Jacobi vector (its 18 vectors never
-// fit); the standard loop streams x, p, r0 and the Jacobi vector when its ten
-// do not (Vecs::far).
+// fit), and when the other eleven do not fit either (Vecs::far, the Mid
+// instantiations of P1 and P3), also p^, q, q^, y, r, r^ and w, which the
+// kernel after next reads back, keeping only z^, v, w^ and t; the standard
+// loop streams x, p, r0 and the Jacobi vector when its ten do not fit
+// (Vecs::far, the Far instantiations of A, C and E).
 template <bool Far>
 __device__ __forceinline__ double ld_v(const double* p) {
   if constexpr (Far) return __builtin_nontemporal_load(p);
@@ -570,7 +574,7 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
 }
 
 // P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
-template <int N, bool Defer = false>
+template <int N, bool Defer = false, bool Mid = false>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
@@ -579,22 +583,22 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
 #pragma unroll
   for (int j = 0; j < 4; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double rh = V.rh[i], w = V.w[i], wh = V.wh[i], r0 = ld_far(&V.r0[i]);
+    const double rh = ld_v<Mid>(&V.rh[i]), w = ld_v<Mid>(&V.w[i]), wh = V.wh[i], r0 = ld_far(&V.r0[i]);
     const double sh_old = ld_far(&V.sh[i]), z_old = ld_far(&V.z[i]);
-    const double ph = fma(beta, fma(-omega, sh_old, V.ph[i]), rh);      // S1
+    const double ph = fma(beta, fma(-omega, sh_old, ld_v<Mid>(&V.ph[i])), rh);  // S1
     const double sv = fma(beta, fma(-omega, z_old, ld_far(&V.s[i])), w);  // S2
     const double sh = fma(beta, fma(-omega, V.zh[i], sh_old), wh);      // S3
     const double z = fma(beta, fma(-omega, V.v[i], z_old), V.t[i]);     // S4
-    const double q = fma(-alpha, sv, V.r[i]);                           // S5
+    const double q = fma(-alpha, sv, ld_v<Mid>(&V.r[i]));               // S5
     const double qh = fma(-alpha, sh, rh);                              // S6
     const double y = fma(-alpha, z, w);                                 // S7
-    V.ph[i] = ph;
+    st_v<Mid>(&V.ph[i], ph);
     st_far(&V.s[i], sv);
     st_far(&V.sh[i], sh);
     st_far(&V.z[i], z);
-    V.q[i] = q;
-    V.qh[i] = qh;
-    V.y[i] = y;
+    st_v<Mid>(&V.q[i], q);
+    st_v<Mid>(&V.qh[i], qh);
+    st_v<Mid>(&V.y[i], y);
     V.zh[i] = ld_far(&A.dinv[i]) * z;                                   // S9
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
@@ -605,7 +609,7 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
 }
 
 // P3: S12..S15, S17 and the partials of <r0,r>, <r0,w> (S16) and <r,r> (slots 0..2)
-template <int N, bool Defer = false>
+template <int N, bool Defer = false, bool Mid = false>
 __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
@@ -615,15 +619,15 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
 #pragma unroll
   for (int j = 0; j < 3; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double qh = V.qh[i], y = V.y[i], r0 = ld_far(&V.r0[i]);
-    const double x = fma(omega, qh, fma(alpha, V.ph[i], ld_far(&V.x[i])));  // S12
-    const double r = fma(-omega, y, V.q[i]);                               // S13
+    const double qh = ld_v<Mid>(&V.qh[i]), y = ld_v<Mid>(&V.y[i]), r0 = ld_far(&V.r0[i]);
+    const double x = fma(omega, qh, fma(alpha, ld_v<Mid>(&V.ph[i]), ld_far(&V.x[i])));  // S12
+    const double r = fma(-omega, y, ld_v<Mid>(&V.q[i]));                               // S13
     const double rh = fma(-omega, fma(-alpha, V.zh[i], V.wh[i]), qh);      // S14
     const double w = fma(-omega, fma(-alpha, V.v[i], V.t[i]), y);          // S15
     st_far(&V.x[i], x);
-    V.r[i] = r;
-    V.rh[i] = rh;
-    V.w[i] = w;
+    st_v<Mid>(&V.r[i], r);
+    st_v<Mid>(&V.rh[i], rh);
+    st_v<Mid>(&V.w[i], w);
     V.wh[i] = ld_far(&A.dinv[i]) * w;                                      // S17
     record_xr(V, iter, A.n, i, x, r);
     d[0].add(r0, r, s.sa, &s.flag[0]);                                 // S16
@@ -801,7 +805,7 @@ __global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
 
 // P1 and P3 leave their reduction to the SpMV kernel that follows them
 // (k_pipe_spmv_fin), and tell its SpMV workgroups whether they ran.
-template <int N>
+template <int N, bool Mid>
 __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   const int done = V.st->done;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
@@ -809,10 +813,10 @@ __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
   shm_init(s, 4);
-  pipe_P1_body<N, true>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P1_body<N, true, Mid>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Mid>
 __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   const int done = V.st->done;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
@@ -820,7 +824,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
   shm_init(s, 3);
-  pipe_P3_body<N, true>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P3_body<N, true, Mid>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 // P2 (W = 1: v = A z^, after P1, finishing S11) and P4 (W = 0: t = A w^, after
