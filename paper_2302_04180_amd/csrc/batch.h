@@ -35,6 +35,8 @@ struct Batch {
   const Tile* tiles;
   const int* order;  // [count[1]] system indices visited by the finishing workgroups
   const int* count;  // [0] number of tiles, [1] number of systems in `order`
+  int far;           // the batch's vectors do not fit in the Infinity Cache: the host
+                     // launches the Far / Mid instantiations (streamed vectors)
 };
 
 // The tile of entry t, uniform over the workgroup: kept (and so the address of
@@ -133,12 +135,12 @@ __global__ void __launch_bounds__(1024) kb_std_init(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) kb_std_A(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_A_body(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { std_A_body<Far>(D.A, D.V, R); });
 }
 
 template <int N>
@@ -150,12 +152,12 @@ __global__ void __launch_bounds__(1024) kb_std_B(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) kb_std_C(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_C_body(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { std_C_body<Far>(D.A, D.V, R); });
 }
 
 template <int N>
@@ -167,12 +169,12 @@ __global__ void __launch_bounds__(1024) kb_std_D(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Far>
 __global__ void __launch_bounds__(1024) kb_std_E(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_E_body<N>(D.A, D.V, D.red, R, rec, s);
+    std_E_body<N, Far>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -206,21 +208,21 @@ __global__ void __launch_bounds__(1024) kb_pipe_init2(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Mid>
 __global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
   tile_loop_publish<N, 4>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P1_body<N, true>(D.A, D.V, D.red, R, rec, s);
+    pipe_P1_body<N, true, Mid>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N>
+template <int N, bool Mid>
 __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
   tile_loop_publish<N, 3>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P3_body<N, true>(D.A, D.V, D.red, R, rec, s);
+    pipe_P3_body<N, true, Mid>(D.A, D.V, D.red, R, rec, s);
   });
 }
 

@@ -213,6 +213,9 @@ Batch batch_of(const Ctx& c) {
   B.sys = (const SysDesc*)(c.ws + c.L.descs);
   B.order = (const int*)(c.ws + c.L.order);
   B.tiles = (const Tile*)(c.ws + c.L.tiles);
+  int64_t rows = 0;
+  for (int64_t v : c.n) rows += v;
+  B.far = rows_stream_far(rows, c.o->variant) ? 1 : 0;
   return B;
 }
 

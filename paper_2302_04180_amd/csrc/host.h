@@ -62,10 +62,12 @@ inline int keep_slices(const rpk_matrix* A, int nvec) {
 // does (Vecs::far): the standard loop when its ten vectors do not fit in nine
 // tenths of the cache, the pipelined loop when the eleven it otherwise keeps
 // do not.
-inline bool streams_far(const rpk_matrix* A, int variant) {
+// A batch of systems decides the same way on its total number of rows.
+inline bool rows_stream_far(int64_t rows, int variant) {
   const int kept = variant == RPK_STD ? nvec_of(RPK_STD) + 2 : variant == RPK_PIPELINED ? 11 : 0;
-  return kept > 0 && (double)kept * (double)A->n * 8.0 > 0.9 * kInfinityCacheBytes;
+  return kept > 0 && (double)kept * (double)rows * 8.0 > 0.9 * kInfinityCacheBytes;
 }
+inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_far(A->n, variant); }
 
 // Vectors of one iteration that stay in the Infinity Cache (the work vectors,
 // x and the Jacobi vector, less those streamed past it)

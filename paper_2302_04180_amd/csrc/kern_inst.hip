@@ -100,11 +100,13 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
   (void)Gf;
   if (variant == RPK_STD) {
     switch (ph) {
-      case 0: return launch(kb_std_A<N>, G, B, 0, s, b);
+      case 0: return b.far ? launch(kb_std_A<N, true>, G, B, 0, s, b) : launch(kb_std_A<N, false>, G, B, 0, s, b);
       case 1: return launch(kb_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, b);
-      case 2: return launch(kb_std_C<N>, G, B, 0, s, b);
+      case 2: return b.far ? launch(kb_std_C<N, true>, G, B, 0, s, b) : launch(kb_std_C<N, false>, G, B, 0, s, b);
       case 3: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
-      default: return launch(kb_std_E<N>, G, B, shm_bytes(N, 2, false, B), s, b);
+      default:
+        return b.far ? launch(kb_std_E<N, true>, G, B, shm_bytes(N, 2, false, B), s, b)
+                     : launch(kb_std_E<N, false>, G, B, shm_bytes(N, 2, false, B), s, b);
     }
   }
   if (variant == RPK_PCG) {
@@ -115,9 +117,13 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
     }
   }
   switch (ph) {
-    case 0: return launch(kb_pipe_P1<N>, G, B, shm_bytes(N, 4, false, B), s, b);
+    case 0:
+      return b.far ? launch(kb_pipe_P1<N, true>, G, B, shm_bytes(N, 4, false, B), s, b)
+                   : launch(kb_pipe_P1<N, false>, G, B, shm_bytes(N, 4, false, B), s, b);
     case 1: return launch(kb_pipe_spmv_fin<N, 1, 4, FIN_POMEGA>, G, B, shm_bytes(N, 4, true, B), s, b);
-    case 2: return launch(kb_pipe_P3<N>, G, B, shm_bytes(N, 3, false, B), s, b);
+    case 2:
+      return b.far ? launch(kb_pipe_P3<N, true>, G, B, shm_bytes(N, 3, false, B), s, b)
+                   : launch(kb_pipe_P3<N, false>, G, B, shm_bytes(N, 3, false, B), s, b);
     default: return launch(kb_pipe_spmv_fin<N, 0, 3, FIN_S19>, G, B, shm_bytes(N, 3, true, B), s, b);
   }
 }

@@ -116,6 +116,7 @@ struct rpk_server {
   State* h_states = nullptr; // pinned
   std::vector<Req*> slots;
   std::vector<int> free_slots;
+  int view_far[NVIEW] = {};  // per view: its systems' vectors do not fit in the Infinity Cache
 
   mutable std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -157,6 +158,7 @@ Batch view(const rpk_server* S, int v) {
   B.sys = (const SysDesc*)(S->hdr + S->off_descs);
   B.order = (const int*)(S->hdr + S->off_order) + (size_t)v * S->o.max_slots;
   B.tiles = (const Tile*)(S->hdr + S->off_tiles) + (size_t)v * S->tile_cap;
+  B.far = S->view_far[v];
   return B;
 }
 
@@ -164,7 +166,12 @@ Batch view(const rpk_server* S, int v) {
 // the number of tiles (a multiple of 8) through *ntiles.
 rpk_status set_view(rpk_server* S, int v, const std::vector<int>& slots_v, int* ntiles) {
   std::vector<int64_t> n;
-  for (int k : slots_v) n.push_back(S->slots[k]->n);
+  int64_t rows = 0;
+  for (int k : slots_v) {
+    n.push_back(S->slots[k]->n);
+    rows += S->slots[k]->n;
+  }
+  S->view_far[v] = rows_stream_far(rows, S->o.solve.variant) ? 1 : 0;
   Plan p;
   if (!slots_v.empty()) p = make_plan(n, S->tile, &slots_v);
   if ((int64_t)p.tiles.size() > S->tile_cap) {
