@@ -78,10 +78,20 @@ typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1, RPK_DOT_FPE = 2 } rpk_dotmo
  * (Fig. 2 / Fig. 3 / Fig. 1 names; a value not computed because the loop stopped is 0.) */
 #define RPK_HIST_W 12
 
-/* Launch shape.  Results of the exact mode do not depend on it. */
+/* Launch shape.  Results of the exact mode do not depend on it.
+ * Carry budget: the digits of the long accumulators are 64-bit words that take
+ * signed 32-bit chunks and propagate carries only when the sum is rounded
+ * (Sec. 3.2 bounds its 52+12 digits by the number of merges in the same way), so
+ * a launch shape is refused (RPK_ERR_ARG, before any device work) when
+ *   - a workgroup would sum more than 2^29 elements (single solves, exdot, exspmv:
+ *     ceil(n / grid) <= 2^29; the automatic grid always fits), or
+ *   - a batched or served system would publish R partial records (its tiles)
+ *     with R * (min(block, tile) * fpe + 1) >= 2^31 (exact dots; e.g. tile 64,
+ *     fpe 8 allows 4.1M tiles, tile 4096 with the defaults any n < 2^31).
+ * Within the budget no digit can overflow, whatever the data. */
 typedef struct {
   int32_t block;  /* workgroup size, a multiple of 64 in [64, 1024]; 0 = 512 */
-  int32_t grid;   /* workgroups of the streaming kernels, >= 1; 0 = automatic */
+  int32_t grid;   /* workgroups of the streaming kernels, 1 .. 65535; 0 = automatic */
   int32_t fpe;    /* FPE length 1, 2, 3, 4 or 8 (1 sends almost every term to
                      the long accumulator); 0 = 3 */
   int32_t graph;  /* solve: iterations per captured HIP graph launch; 0 = automatic,
@@ -118,7 +128,9 @@ typedef struct {
   double latency_ms;   /* server: submission -> result ready                     */
   int32_t inexact_dots; /* RPK_DOT_FPE: dot products that could not keep every bit
                            (0: the solve is bit-identical to RPK_DOT_EXACT)       */
-  int32_t reserved;
+  int32_t streamed;    /* 1: the vectors that did not fit in the Infinity Cache beside
+                          the rest were read and written non-temporally (a speed
+                          choice made from the rows in flight; results are the same) */
 } rpk_info;
 
 typedef struct rpk_matrix rpk_matrix;
@@ -153,7 +165,8 @@ rpk_status rpk_exdot_workspace_bytes(int64_t n, const rpk_launch* launch, size_t
 
 /* *out_dev = RN(sum_i x[i]*y[i]) of the exact sum (Sec. 2, exdot), one device double.
  * Exact zero gives +0.0; a non-zero sum that rounds to zero keeps its sign; an
- * overflowing sum gives +-inf; any non-finite factor gives NaN.  n < 2^32.
+ * overflowing sum gives +-inf; any non-finite factor gives NaN.  n < 2^32, with
+ * ceil(n / grid) <= 2^29 (carry budget, see rpk_launch).
  * dots = RPK_DOT_PLAIN gives the non-reproducible fma/tree-reduction value instead.
  * Asynchronous on `stream`. */
 rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
@@ -193,6 +206,14 @@ rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* opts, 
  * A workspace whose solve stopped for another reason returns that status. */
 rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_opts* opts, void* ws,
                      size_t ws_bytes, void* stream, rpk_info* info);
+
+/* Host only (no device work): RPK_OK when rpk_solve_batched accepts systems of
+ * n[0..nsys-1] rows with these options -- valid variant, dots and launch, and at
+ * least one configuration (the caller's tile, or one of the autotuner's
+ * candidates when launch.tile = 0) within the carry budget above for every
+ * system; RPK_ERR_ARG otherwise.  rpk_solve_batched and its workspace query
+ * apply the same check to the matrices' sizes. */
+rpk_status rpk_batched_check(int32_t nsys, const int64_t* n, const rpk_opts* opts);
 
 /* Workspace size of rpk_solve_batched for these nsys systems and options. */
 rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* opts,
@@ -260,7 +281,8 @@ rpk_status rpk_server_footprint(const rpk_server* s, const rpk_matrix* A, size_t
  * be in place (work that writes them completed) when this is called; x is
  * complete when poll/wait report the request finished.  *ticket identifies the
  * request.  RPK_REJECTED: its footprint exceeds the whole budget (nothing
- * queued). */
+ * queued).  RPK_ERR_ARG: A's tiles would exceed the carry budget (see
+ * rpk_launch) at the server's tile, workgroup size and FPE length. */
 rpk_status rpk_server_submit(rpk_server* s, const rpk_matrix* A, const double* b, double* x, uint64_t* ticket);
 
 /* RPK_PENDING while the request runs or waits; once finished, fills *info

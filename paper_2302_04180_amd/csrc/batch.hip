@@ -9,7 +9,8 @@
 //   trial  : one x per system (only when the autotuner may run)
 // The header is written with one host-to-device copy per call; everything the
 // kernels need is found through it, so a cached graph only depends on the
-// workspace address and the launch shape.
+// workspace address, the launch shape and whether the batch's far vectors are
+// streamed (which picks the kernel instantiations captured).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -335,6 +336,44 @@ rpk_status trial_time(const Ctx& c, const BCfg& cfg, float* ms) {
 
 std::map<std::vector<int64_t>, BCfg> g_tuned;  // guarded by lib_mutex()
 
+// Every system's reduction records (its tiles) fit the carry budget of the long
+// accumulators at this tile / workgroup / FPE length (plain sums have none).
+bool plan_fits(const Plan& plan, const BCfg& cfg, bool plain) {
+  const int64_t lanes = std::min(cfg.block, cfg.tile);
+  for (int g : plan.G)
+    if (!records_fit(g, lanes, plain ? 0 : cfg.fpe)) return false;
+  return true;
+}
+
+// The configurations rpk_solve_batched may run: the caller's tile, or the
+// autotuner's candidates (tile rows x workgroup size x FPE length, with the
+// caller's workgroup size / FPE length where given), those that fit the carry
+// budget for systems of n rows.
+std::vector<BCfg> configs_for(const std::vector<int64_t>& n, const rpk_opts* o) {
+  const bool plain = o->dots == RPK_DOT_PLAIN;
+  std::vector<BCfg> out;
+  if (o->launch.tile) {
+    out.push_back(BCfg{o->launch.tile, o->launch.block ? o->launch.block : 512, o->launch.fpe ? o->launch.fpe : 3,
+                       o->launch.graph, o->launch.grid});
+  } else {
+    struct Cand {
+      int tile, block, fpe;
+    };
+    const Cand all[] = {{1024, 256, 3}, {2048, 512, 3}, {4096, 512, 3}, {8192, 512, 3},
+                        {4096, 1024, 3}, {16384, 1024, 3}, {4096, 512, 4}, {4096, 512, 2}};
+    for (const Cand& cd : all) {
+      if (plain && cd.fpe != 3) continue;  // the FPE length does not exist in plain mode
+      if (cd.tile < kTileMinAuto) continue;
+      out.push_back(BCfg{cd.tile, o->launch.block ? o->launch.block : cd.block,
+                         o->launch.fpe ? o->launch.fpe : cd.fpe, -1, o->launch.grid});
+    }
+  }
+  std::vector<BCfg> fit;
+  for (const BCfg& cfg : out)
+    if (plan_fits(make_plan(n, cfg.tile), cfg, plain)) fit.push_back(cfg);
+  return fit;
+}
+
 rpk_status autotune(const Ctx& c, BCfg* best) {
   int64_t sum_n = 0, sum_nnz = 0, max_n = 0;
   for (int k = 0; k < c.ns; ++k) {
@@ -351,18 +390,10 @@ rpk_status autotune(const Ctx& c, BCfg* best) {
     best->graph = c.o->launch.graph;
     return RPK_OK;
   }
-  // candidates: tile rows x workgroup size x FPE length (only the given ones if fixed)
-  struct Cand {
-    int tile, block, fpe;
-  };
-  const Cand all[] = {{1024, 256, 3}, {2048, 512, 3}, {4096, 512, 3}, {8192, 512, 3},
-                      {4096, 1024, 3}, {16384, 1024, 3}, {4096, 512, 4}, {4096, 512, 2}};
+  const std::vector<BCfg> cands = configs_for(c.n, c.o);
+  if (cands.empty()) return RPK_ERR_ARG;
   float best_ms = -1.f;
-  for (const Cand& cd : all) {
-    BCfg cfg{cd.tile, c.o->launch.block ? c.o->launch.block : cd.block,
-             c.o->launch.fpe ? c.o->launch.fpe : cd.fpe, -1, c.o->launch.grid};
-    if (plain && cd.fpe != 3) continue;  // the FPE length does not exist in plain mode
-    if (cfg.tile < kTileMinAuto) continue;
+  for (const BCfg& cfg : cands) {
     float ms = 0.f;
     RET_IF(trial_time(c, cfg, &ms));
     if (best_ms < 0.f || ms < best_ms) {
@@ -391,6 +422,7 @@ rpk_status run(const Ctx& c, const BCfg& cfg, rpk_info* infos) {
     infos[0].phase_launches[slot] += 1;
   };
   State* h = nullptr;
+  const int bt_far = batch_of(c).far;
   do {
     if (st != RPK_OK) break;
     if (timing && hipEventRecord(ev[0], c.s) != hipSuccess) { st = RPK_ERR_HIP; break; }
@@ -424,7 +456,7 @@ rpk_status run(const Ctx& c, const BCfg& cfg, rpk_info* infos) {
         const std::vector<uint64_t> key{0, (uint64_t)(uintptr_t)c.ws, (uint64_t)c.L.count, (uint64_t)c.L.descs,
                                         (uint64_t)c.L.order, (uint64_t)c.L.tiles, (uint64_t)c.o->variant,
                                         (uint64_t)sh.N, (uint64_t)sh.G, (uint64_t)sh.Gf, (uint64_t)sh.B,
-                                        (uint64_t)chunk, 0xba7c4ull};
+                                        (uint64_t)chunk, (uint64_t)bt.far, 0xba7c4ull};
         hipGraphExec_t exec = nullptr;
         st = graph_get(key, [&](hipStream_t cs) {
           rpk_status cst = RPK_OK;
@@ -471,6 +503,7 @@ rpk_status run(const Ctx& c, const BCfg& cfg, rpk_info* infos) {
     I.used.fpe = sh.N;
     I.used.graph = cfg.graph;
     I.used.tile = cfg.tile;
+    I.streamed = bt_far;
     if (first == RPK_OK && h[k].status != RPK_OK) first = (rpk_status)h[k].status;
   }
   return first;
@@ -484,6 +517,7 @@ rpk_status prepare(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* o, 
     if (!A[k]) return RPK_ERR_ARG;
     (*n)[k] = A[k]->n;
   }
+  if (configs_for(*n, o).empty()) return RPK_ERR_ARG;  // over the carry budget
   return RPK_OK;
 }
 
@@ -507,6 +541,15 @@ rpk_status rpk_plan_tiles(int32_t nsys, const int64_t* n, int32_t tile, int32_t*
     tiles[4 * t + 3] = p.tiles[t].rec;
   }
   return RPK_OK;
+}
+
+rpk_status rpk_batched_check(int32_t nsys, const int64_t* n, const rpk_opts* opts) {
+  if (nsys < 1 || nsys > kMaxSys || !n) return RPK_ERR_ARG;
+  RET_IF(check_opts(opts));
+  std::vector<int64_t> nv(n, n + nsys);
+  for (int64_t v : nv)
+    if (v < 1 || v >= (1ll << 31)) return RPK_ERR_ARG;
+  return configs_for(nv, opts).empty() ? RPK_ERR_ARG : RPK_OK;
 }
 
 rpk_status rpk_solve_batched_workspace_bytes(int32_t nsys, const rpk_matrix* const* A, const rpk_opts* o,
@@ -541,8 +584,7 @@ rpk_status rpk_solve_batched(int32_t nsys, const rpk_matrix* const* A, const dou
   RET_IF(ensure_globals());
   BCfg cfg;
   if (tile) {
-    cfg = BCfg{tile, o->launch.block ? o->launch.block : 512, o->launch.fpe ? o->launch.fpe : 3, o->launch.graph,
-               o->launch.grid};
+    cfg = configs_for(c.n, o)[0];  // prepare() checked that it fits
   } else {
     RET_IF(autotune(c, &cfg));
   }

@@ -37,6 +37,26 @@ using namespace rpk;
 constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Carry budget of the exact reductions.  Long-accumulator digits are int64
+// words that receive signed 32-bit chunks and propagate no carry until the final
+// rounding, so the number of chunks a digit can receive is what bounds a sum
+// (Sec. 3.2 bounds the merges of its 52+12 split the same way):
+//   - a workgroup's LDS accumulator takes, per digit, at most two chunks per
+//     product it sums (the twoprod terms p and e) plus one per FPE component it
+//     flushes: kMaxPerGroup elements per workgroup keep 2^30 + 8*1024 chunks of
+//     < 2^32 below 2^63;
+//   - a global accumulator takes, per digit and per published record, at most
+//     one chunk per FPE component of every lane that had data, plus one digit of
+//     the workgroup's normalised LDS accumulator: a reduction of R records from
+//     L lanes with FPE length N stays below 2^63 when R (L N + 1) < 2^31.
+// Single solves always fit the second rule (grid <= 65535, L <= 1024, N <= 8);
+// the batched solver and the server check it per system (records = tiles).
+constexpr int64_t kMaxPerGroup = int64_t(1) << 29;
+constexpr int64_t kCarryChunks = (int64_t(1) << 31) - 1;
+inline bool records_fit(int64_t records, int64_t lanes, int fpe) {
+  return records * (lanes * (int64_t)fpe + 1) <= kCarryChunks;
+}
+
 inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert, 0}; }
 
 inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK_PCG ? 4 : 16; }

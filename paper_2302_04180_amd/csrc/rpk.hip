@@ -46,6 +46,10 @@ rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
     if (need >= 8) need &= ~7ll;
     c->grid = (int)need;
   }
+  // carry budget of the workgroups' long accumulators (a fixed small grid
+  // cannot take a huge n)
+  if ((n + c->grid - 1) / c->grid > kMaxPerGroup) return RPK_ERR_ARG;
+  if (!records_fit(c->grid, c->block, c->fpe)) return RPK_ERR_ARG;
   return RPK_OK;
 }
 
@@ -196,6 +200,8 @@ const char* rpk_status_str(int32_t s) {
     case RPK_ERR_NONFINITE: return "RPK_ERR_NONFINITE";
     case RPK_NOT_CONVERGED: return "RPK_NOT_CONVERGED";
     case RPK_BREAKDOWN: return "RPK_BREAKDOWN";
+    case RPK_PENDING: return "RPK_PENDING";
+    case RPK_REJECTED: return "RPK_REJECTED";
   }
   return "RPK_UNKNOWN";
 }
@@ -448,6 +454,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   info->used.grid = c.grid;
   info->used.fpe = (o->dots == RPK_DOT_PLAIN) ? 0 : (o->dots == RPK_DOT_FPE) ? LW_N : c.fpe;
   info->used.graph = c.graph;
+  info->streamed = streams_far(A, o->variant) ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
   RET_IF(ensure_globals());

@@ -90,6 +90,7 @@ struct Req {
   size_t bytes = 0, off = 0;
   int slot = -1;
   bool finished = false;
+  bool streamed = false;  // some round ran it with the far vectors streamed
   Clock::time_point t_submit, t_admit;
   rpk_info info;
 };
@@ -237,6 +238,8 @@ rpk_status round(rpk_server* S, const std::vector<int>& fresh, const std::vector
   }
   RET_IF(set_view(S, V_NEW, fresh, &nt_new));
   RET_IF(set_view(S, V_RUN, running, &nt_run));
+  if (S->view_far[V_RUN])
+    for (int k : running) S->slots[k]->streamed = true;
   RET_IF(upload(S));
   if (!fresh.empty())
     RET_IF(by_fpe<SStartF>(S->N, variant, g_of(nt_new), gf_of(fresh.size()), S->block, S->stream, view(S, V_NEW),
@@ -333,6 +336,7 @@ void worker_main(rpk_server* S) {
       I.used.fpe = S->N;
       I.used.tile = S->tile;
       I.used.graph = -1;
+      I.streamed = r->streamed ? 1 : 0;
       I.queue_ms = ms_between(r->t_submit, r->t_admit);
       I.latency_ms = ms_between(r->t_submit, now);
       r->finished = true;
@@ -430,6 +434,9 @@ rpk_status rpk_server_footprint(const rpk_server* s, const rpk_matrix* A, size_t
 
 rpk_status rpk_server_submit(rpk_server* s, const rpk_matrix* A, const double* b, double* x, uint64_t* ticket) {
   if (!s || !A || !b || !x || !ticket) return RPK_ERR_ARG;
+  const int64_t gcap = std::max<int64_t>(1, (A->n + s->tile - 1) / s->tile);
+  // the request's reduction records (its tiles) must fit the carry budget
+  if (!records_fit(gcap, std::min(s->block, s->tile), s->N)) return RPK_ERR_ARG;
   const size_t bytes = footprint(s, A->n);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->failure != RPK_OK) return s->failure;
@@ -445,7 +452,7 @@ rpk_status rpk_server_submit(rpk_server* s, const rpk_matrix* A, const double* b
   r->b = b;
   r->x = x;
   r->n = A->n;
-  r->gcap = (int)std::max<int64_t>(1, (A->n + s->tile - 1) / s->tile);
+  r->gcap = (int)gcap;
   r->bytes = bytes;
   r->t_submit = Clock::now();
   std::memset(&r->info, 0, sizeof(r->info));

@@ -37,7 +37,7 @@ class Info(ctypes.Structure):
                 ("tau", ctypes.c_double), ("true_res", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 12), ("phase_launches", ctypes.c_int32 * 12),
                 ("used", Launch), ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
-                ("inexact_dots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("inexact_dots", ctypes.c_int32), ("streamed", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -54,8 +54,8 @@ class ServerStats(ctypes.Structure):
 
 EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
            "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot", "rpk_fpedot",
-           "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_solve_batched_workspace_bytes",
-           "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
+           "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_batched_check",
+           "rpk_solve_batched_workspace_bytes", "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
            "rpk_server_poll", "rpk_server_wait", "rpk_server_get_stats", "rpk_server_destroy",
            "rpk_plan_tiles", "rpk_device_divsqrt"]
 
@@ -82,6 +82,7 @@ def load(path=LIB_PATH):
     lib.rpk_exdot_workspace_bytes.argtypes = [I64, ctypes.POINTER(Launch), ctypes.POINTER(S)]
     lib.rpk_exdot.argtypes = [I64, P, P, P, I32, ctypes.POINTER(Launch), P, S, P]
     lib.rpk_fpedot.argtypes = [I64, P, P, P, P, ctypes.POINTER(Launch), P, S, P]
+    lib.rpk_batched_check.argtypes = [I32, P, ctypes.POINTER(Opts)]
     lib.rpk_exspmv.argtypes = [P, P, P, I32, ctypes.POINTER(Launch), P]
     lib.rpk_solve_workspace_bytes.argtypes = [P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
     lib.rpk_solve.argtypes = [P, P, P, ctypes.POINTER(Opts), P, S, P, ctypes.POINTER(Info)]
@@ -322,7 +323,8 @@ def _info_dict(info):
             "tau0": info.tau0, "tau": info.tau, "true_res": info.true_res,
             "phase_ms": list(info.phase_ms), "phase_launches": list(info.phase_launches),
             "used": {"block": u.block, "grid": u.grid, "fpe": u.fpe, "graph": u.graph, "tile": u.tile},
-            "queue_ms": info.queue_ms, "latency_ms": info.latency_ms, "inexact_dots": info.inexact_dots}
+            "queue_ms": info.queue_ms, "latency_ms": info.latency_ms, "inexact_dots": info.inexact_dots,
+            "streamed": bool(info.streamed)}
 
 
 def solve_batched(As, bs, x0s=None, tol=1e-8, maxit=500, variant=STD, dots=EXACT, block=0, grid=0, fpe=0,

@@ -18,6 +18,13 @@ def declared():
     return sorted(set(re.findall(r"\b(rpk_[a-z_0-9]+)\s*\(", text)))
 
 
+def status_codes():
+    """name -> value of every enumerator of rpk_status in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef enum \{(.*?)\} rpk_status;", text, flags=re.S).group(1)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"(RPK_[A-Z_]+)\s*=\s*(\d+)", body)}
+
+
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("rpk_matrix_create", "rpk_matrix_destroy", "rpk_exdot", "rpk_exspmv", "rpk_solve"):
@@ -48,7 +55,12 @@ def test_host_only_entry_points(lib):
     lib.rpk_version.restype = ctypes.c_char_p
     assert b"gfx950" in lib.rpk_version()
     lib.rpk_status_str.restype = ctypes.c_char_p
-    assert lib.rpk_status_str(7) == b"RPK_BREAKDOWN"
+    codes = status_codes()
+    assert len(codes) >= 10
+    for name, value in codes.items():  # every status the header declares has its own name
+        assert lib.rpk_status_str(value) == name.encode(), (name, value)
+    assert lib.rpk_status_str(max(codes.values()) + 1) == b"RPK_UNKNOWN"
+    assert lib.rpk_status_str(-1) == b"RPK_UNKNOWN"
     lib.rpk_exdot_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
     nb = ctypes.c_size_t()
     assert lib.rpk_exdot_workspace_bytes(1000, None, ctypes.byref(nb)) == 0 and nb.value > 0
@@ -93,3 +105,49 @@ def test_binding_checks_matrix_arguments_on_the_host():
     with pytest.raises(ValueError):  # host tensors are not device arrays
         rpk.Matrix.from_tensors(torch.zeros(3, dtype=torch.int32), torch.zeros(2, dtype=torch.int32),
                                 torch.zeros(2, dtype=torch.float64))
+
+
+def test_carry_budget_host_checks(lib):
+    """Launch shapes whose long-accumulator digits could overflow are refused
+    before any device work (the budget is stated with rpk_launch in the header)."""
+    P = ctypes.c_void_p
+
+    class Launch(ctypes.Structure):
+        _fields_ = [(f, ctypes.c_int32) for f in ("block", "grid", "fpe", "graph", "tile")]
+
+    lib.rpk_exdot_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    nb = ctypes.c_size_t()
+    big = (1 << 31) + 5
+    # a workgroup may sum at most 2^29 elements: grid 4 cannot take 2^31 + 5, grid 5 can
+    assert lib.rpk_exdot_workspace_bytes(big, ctypes.byref(Launch(0, 4, 1, 0, 0)), ctypes.byref(nb)) == 1
+    assert lib.rpk_exdot_workspace_bytes(big, ctypes.byref(Launch(0, 5, 1, 0, 0)), ctypes.byref(nb)) == 0
+    assert lib.rpk_exdot_workspace_bytes(1 << 29, ctypes.byref(Launch(0, 1, 1, 0, 0)), ctypes.byref(nb)) == 0
+    assert lib.rpk_exdot_workspace_bytes((1 << 29) + 1, ctypes.byref(Launch(0, 1, 1, 0, 0)),
+                                         ctypes.byref(nb)) == 1
+    assert lib.rpk_exdot_workspace_bytes((1 << 32) - 1, None, ctypes.byref(nb)) == 0  # automatic grid
+    lib.rpk_exdot.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, ctypes.c_size_t, P]
+    assert lib.rpk_exdot(big, P(8), P(8), P(8), 0, ctypes.byref(Launch(0, 2, 1, 0, 0)), P(8), 1 << 40,
+                         None) == 1
+
+    class Opts(ctypes.Structure):
+        _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("variant", ctypes.c_int32),
+                    ("dots", ctypes.c_int32), ("timing", ctypes.c_int32), ("resume", ctypes.c_int32),
+                    ("launch", Launch), ("hist", P), ("xr_hist", P)]
+
+    lib.rpk_batched_check.argtypes = [ctypes.c_int32, P, P]
+
+    def check(ns, tile, block, fpe, dots=0):
+        n = (ctypes.c_int64 * len(ns))(*ns)
+        o = Opts(1e-8, 10, 0, dots, 0, 0, Launch(block, 0, fpe, 0, tile), None, None)
+        return lib.rpk_batched_check(len(ns), n, ctypes.byref(o))
+
+    # R * (min(block, tile) * fpe + 1) < 2^31: tile 64, fpe 8 -> 513 chunks per record, 4,186,127 records
+    lim = ((1 << 31) - 1) // 513
+    assert check([64 * lim], 64, 512, 8) == 0
+    assert check([64 * lim + 1], 64, 512, 8) == 1
+    assert check([1000, 64 * lim + 1], 64, 512, 8) == 1       # one system over the budget refuses the batch
+    assert check([64 * lim + 1], 64, 512, 8, dots=1) == 0      # plain sums carry no digits
+    assert check([64 * lim + 1], 128, 512, 8) == 0             # larger tiles: fewer records
+    assert check([(1 << 31) - 1], 0, 0, 0) == 0                # the autotuner's candidates fit any n
+    assert check([(1 << 31) - 1], 4096, 0, 0) == 0
+    assert check([0], 4096, 0, 0) == 1 and check([1 << 31], 4096, 0, 0) == 1

@@ -33,6 +33,8 @@ def alone(M, b, variant):
 
 
 def check(k, x, info, xa, ia):
+    # the pair (4.2M rows) took the streaming instantiations, each system alone the cached ones
+    assert info["streamed"] and not ia["streamed"], (k, info["streamed"], ia["streamed"])
     assert info["status"] == ia["status"] and info["iters"] == ia["iters"], (k, info["iters"], ia["iters"])
     assert same(info["tau"], ia["tau"]) and same(info["true_res"], ia["true_res"]), k
     assert same(x, xa), (k, first_diff(x, xa))

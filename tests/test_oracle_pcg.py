@@ -10,6 +10,7 @@
   iterate;
 * closed forms: a diagonal system with power-of-two entries converges in one
   iteration to x = b / a exactly; a zero right-hand side needs no iteration."""
+import math
 from fractions import Fraction as F
 
 import numpy as np
@@ -89,6 +90,11 @@ def test_oracle_pcg_equals_ieee_bruteforce(orc, name, A, xs):
                 assert all(same_bits(a, bb) for a, bb in zip(res["xr"][j, 0].tolist(), rec["x"]))
                 assert all(same_bits(a, bb) for a, bb in zip(res["xr"][j, 1].tolist(), rec["r"]))
         assert all(same_bits(a, bb) for a, bb in zip(res["x"].tolist(), x))
+        # the exit residual ||b - A x|| recomputed from rationals (Table 1's true residual)
+        rp, ci, v = as_lists(A)
+        t = fracref.exact_rowsums(rp, ci, v, x)
+        e = [fracref.rn(F(bi) - F(ti)) for bi, ti in zip(b.tolist(), t)]
+        assert same_bits(res["true_res"], math.sqrt(fracref.exact_dot(e, e))), name
 
 
 def test_pcg_diagonal_pow2_one_iteration(orc):

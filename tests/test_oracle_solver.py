@@ -8,6 +8,10 @@
   scalar and every iterate.
 * Closed forms (diagonal systems), invariants (symmetric permutation, thread
   count, maxit truncation) and a convergence sanity check on the 16^3 problem.
+* The reported true residual (Table 1's column, ||b - A x|| of the returned x)
+  recomputed in rationals from its definition: e_i = RN(b_i - RN(sum_j a_ij x_j)),
+  RN(sqrt(RN(sum_i e_i^2))), on runs where the recurrence residual differs from
+  b - A x and a plain sum of squares differs from the exact one.
 """
 import math
 from fractions import Fraction as F
@@ -90,6 +94,16 @@ def test_exact_arithmetic_std_equals_pipelined(name, A, xs):
         assert a["omega"] == c["omega"] and a["rho_new"] == c["rho_new"]
 
 
+def true_residual_ref(A, b, x):
+    """||b - A x||_2 as the oracle must report it, from rationals: every row sum
+    and the sum of squares exact and rounded once, b_i - t_i rounded once, then
+    CPython's correctly rounded square root."""
+    rp, ci, v = _as_lists(A)
+    t = fracref.exact_rowsums(rp, ci, v, [float(a) for a in x])
+    e = [fracref.rn(F(bi) - F(ti)) for bi, ti in zip(np.asarray(b).tolist(), t)]
+    return math.sqrt(fracref.exact_dot(e, e)), e
+
+
 def _compare_to_bruteforce(orc, A, b, x0, tol, maxit, variant):
     Al = _as_lists(A)
     trace = []
@@ -108,6 +122,7 @@ def _compare_to_bruteforce(orc, A, b, x0, tol, maxit, variant):
             assert all(same_bits(a, bb) for a, bb in zip(res["xr"][j, 0].tolist(), rec["x"]))
             assert all(same_bits(a, bb) for a, bb in zip(res["xr"][j, 1].tolist(), rec["r"]))
     assert all(same_bits(a, bb) for a, bb in zip(res["x"].tolist(), x))
+    assert same_bits(res["true_res"], true_residual_ref(A, b, x)[0])
     return res
 
 
@@ -236,3 +251,63 @@ def test_zero_rhs(orc):
     A = inputs.poisson7(3)
     res = orc.solve(*A, np.zeros(27), tol=1e-8, maxit=10)
     assert res["status"] == "OK" and res["iters"] == 0 and res["tau0"] == 0.0
+
+
+def _true_res_cases():
+    out = []
+    for s in range(4):
+        A = inputs.tiny_nonsym(7 + s, 300 + s)
+        out.append((A, inputs.uniform(7 + s, 310 + s), inputs.uniform(7 + s, 320 + s) * 0.25, 2 + s))
+    A = inputs.convdiff7(3, (1.3, 0.65, 0.325))
+    out.append((A, inputs.uniform(27, 330), None, 3))
+    A = inputs.poisson7(3)
+    out.append((A, inputs.uniform(27, 331) * 1e3, inputs.uniform(27, 332), 4))
+    return out
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_true_residual_against_rational_definition(orc, variant):
+    """The exit residual is ||b - A x|| of the returned x with exact rows and an
+    exact sum of squares (Table 1's true residual, Sec. 5.1).  The cases are
+    solves stopped at their iteration limit, where the recurrence residual r_j
+    no longer equals b - A x_j in every bit; leaving out the square root or
+    taking the recurrence r in place of b - A x must change the value on at
+    least one of them (a plain sum of squares is caught by the closed forms)."""
+    slips = {"no_sqrt": 0, "recurrence_r": 0}
+    for A, b, x0, maxit in _true_res_cases():
+        res = orc.solve(*A, b, x0=x0, tol=0.0, maxit=maxit, variant=variant, record_xr=True)
+        assert res["status"] == "NOT_CONVERGED" and res["iters"] == maxit
+        ref, e = true_residual_ref(A, b, res["x"])
+        assert ref > 0.0 and same_bits(res["true_res"], ref), (res["true_res"], ref)
+        r = res["xr"][maxit - 1, 1].tolist()
+        slips["no_sqrt"] += fracref.exact_dot(e, e) != ref
+        slips["recurrence_r"] += math.sqrt(fracref.exact_dot(r, r)) != ref
+    assert all(v > 0 for v in slips.values()), slips
+
+
+def _diag(d):
+    n = len(d)
+    return (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.asarray(d, dtype=np.float64))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_true_residual_closed_forms(orc, variant):
+    """maxit = 0 returns x0, so the true residual is ||b - A x0||.
+    * A = diag(2, 4), x0 = (1, 1), b = (5, 8): e = (3, 4), exactly 5.
+    * A = I, x0 = 0, b = (1, 1): RN(sqrt(2)).
+    * A = I (17 rows), x0 = 0, b = (1, 2^-27 x 16): the exact sum of squares is
+      1 + 2^-50, its root rounds to 1 + 2^-51; a plain sum of squares from the
+      first element on (additions or fmas) keeps 1 and gives 1."""
+    res = orc.solve(*_diag([2.0, 4.0]), np.array([5.0, 8.0]), x0=np.array([1.0, 1.0]), tol=1e-12, maxit=0,
+                    variant=variant)
+    assert res["status"] == "NOT_CONVERGED" and res["iters"] == 0
+    assert same_bits(res["true_res"], 5.0)
+    res = orc.solve(*_diag([1.0, 1.0]), np.array([1.0, 1.0]), tol=1e-12, maxit=0, variant=variant)
+    assert same_bits(res["true_res"], float.fromhex("0x1.6a09e667f3bcdp+0"))
+    b = np.array([1.0] + [2.0 ** -27] * 16)
+    res = orc.solve(*_diag([1.0] * 17), b, tol=1e-12, maxit=0, variant=variant)
+    assert same_bits(res["true_res"], 1.0 + 2.0 ** -51)
+    plain = 0.0
+    for v in b.tolist():
+        plain = fracref.fma(v, v, plain)
+    assert math.sqrt(plain) == 1.0
