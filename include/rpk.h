@@ -172,6 +172,22 @@ rpk_status rpk_exdot_workspace_bytes(int64_t n, const rpk_launch* launch, size_t
 rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
                      const rpk_launch* launch, void* ws, size_t ws_bytes, void* stream);
 
+/* rpk_exdot for callers that cannot allocate device memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * kernels and results (bit for bit) as rpk_exdot with this n, dots and launch,
+ * but no workspace argument: the reduction scratch is a 1 MiB array in device
+ * memory that the library holds on every device it runs on until the process
+ * ends.  The call itself allocates nothing (no hipMalloc / hipFree, no
+ * allocating library routine); it clears the scratch's counters with a small
+ * kernel before the dot, so it can be captured into a graph.  Limit: the launch
+ * may use at most 1,624 workgroups (the automatic grid never exceeds 512), else
+ * RPK_ERR_ARG.  All calls on one device share its scratch: calls that overlap
+ * in time on one device (two streams, two threads, two graphs in flight) race
+ * and give wrong results; calls ordered on one stream do not.
+ * Asynchronous on `stream`. */
+rpk_status rpk_exdot_noalloc(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
+                             const rpk_launch* launch, void* stream);
+
 /* Lightweight dot (Sec. 3.2, RPK_DOT_FPE): *out_dev = RN of the sum held by the
  * merged FPE-8s, plus, when something did not fit, the lost part added in plain
  * FP64; *lost_dev (one device int32) = 0 when every bit was kept -- then

@@ -20,6 +20,15 @@
 using namespace rpk;
 using namespace rpkhost;
 
+// Reduction scratch of rpk_exdot_noalloc: one copy on every device the library
+// runs on, held until the process ends.  Host code must not use this name as a
+// device address: it is a host-side stand-in.  The address of each device's
+// copy comes from hipGetSymbolAddress, taken once per device (noalloc_scratch).
+// Holds the exdot workspace layout (header + per-workgroup partial records) of
+// grids up to 1,624 workgroups.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 struct Cfg {
@@ -129,6 +138,27 @@ std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
 hipStream_t g_capture = nullptr;
 State* g_pinned = nullptr;
 size_t g_pinned_count = 0;
+
+// Device address of this device's copy of `scratch` (rpk_exdot_noalloc), taken
+// with hipGetSymbolAddress on the first call with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+rpk_status noalloc_scratch(char** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return RPK_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RPK_ERR_HIP;
+    g_scratch[dev] = (char*)p;
+  }
+  *out = g_scratch[dev];
+  return RPK_OK;
+}
 
 }  // namespace
 
@@ -382,6 +412,26 @@ rpk_status rpk_exdot(int64_t n, const double* x, const double* y, double* out_de
   Red red = make_red((char*)ws, l, c.grid);
   const int N = kernel_n(dots, c.fpe);
   return by_dot<DotF>(N, c.grid, c.block, (hipStream_t)stream, (long long)n, x, y, out_dev, (int*)nullptr, red);
+}
+
+rpk_status rpk_exdot_noalloc(int64_t n, const double* x, const double* y, double* out_dev, int32_t dots,
+                             const rpk_launch* launch_cfg, void* stream) {
+  if (n < 0 || n >= (1ll << 32) || !out_dev || (n > 0 && (!x || !y))) return RPK_ERR_ARG;
+  if (dots != RPK_DOT_EXACT && dots != RPK_DOT_PLAIN) return RPK_ERR_ARG;
+  Cfg c;
+  RET_IF(resolve(launch_cfg, n, &c));
+  const Layout l = layout(c.grid, 0, 0);
+  if (l.total > kScratchBytes) return RPK_ERR_ARG;  // grid beyond what the scratch array holds
+  char* ws = nullptr;
+  RET_IF(noalloc_scratch(&ws));
+  hipStream_t s = (hipStream_t)stream;
+  // tickets, flags and long accumulators start at zero (the kernel leaves them
+  // zeroed; cleared all the same, by a kernel rather than a memset node)
+  hipLaunchKernelGGL(k_zero_words, dim3(4), dim3(256), 0, s, (unsigned*)ws,
+                     (long long)(l.partials / sizeof(unsigned)));
+  if (hipGetLastError() != hipSuccess) return RPK_ERR_HIP;
+  Red red = make_red(ws, l, c.grid);
+  return by_dot<DotF>(kernel_n(dots, c.fpe), c.grid, c.block, s, (long long)n, x, y, out_dev, (int*)nullptr, red);
 }
 
 rpk_status rpk_fpedot(int64_t n, const double* x, const double* y, double* out_dev, int32_t* lost_dev,

@@ -53,7 +53,8 @@ class ServerStats(ctypes.Structure):
 
 
 EXPORTS = ["rpk_version", "rpk_status_str", "rpk_matrix_create", "rpk_matrix_destroy",
-           "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot", "rpk_fpedot",
+           "rpk_matrix_dims", "rpk_matrix_dinv", "rpk_exdot_workspace_bytes", "rpk_exdot", "rpk_exdot_noalloc",
+           "rpk_fpedot",
            "rpk_exspmv", "rpk_solve_workspace_bytes", "rpk_solve", "rpk_batched_check",
            "rpk_solve_batched_workspace_bytes", "rpk_solve_batched", "rpk_server_create", "rpk_server_footprint", "rpk_server_submit",
            "rpk_server_poll", "rpk_server_wait", "rpk_server_get_stats", "rpk_server_destroy",
@@ -82,6 +83,7 @@ def load(path=LIB_PATH):
     lib.rpk_exdot_workspace_bytes.argtypes = [I64, ctypes.POINTER(Launch), ctypes.POINTER(S)]
     lib.rpk_exdot.argtypes = [I64, P, P, P, I32, ctypes.POINTER(Launch), P, S, P]
     lib.rpk_fpedot.argtypes = [I64, P, P, P, P, ctypes.POINTER(Launch), P, S, P]
+    lib.rpk_exdot_noalloc.argtypes = [I64, P, P, P, I32, ctypes.POINTER(Launch), P]
     lib.rpk_batched_check.argtypes = [I32, P, ctypes.POINTER(Opts)]
     lib.rpk_exspmv.argtypes = [P, P, P, I32, ctypes.POINTER(Launch), P]
     lib.rpk_solve_workspace_bytes.argtypes = [P, ctypes.POINTER(Opts), ctypes.POINTER(S)]
@@ -234,6 +236,19 @@ def exdot(x, y, dots=EXACT, block=0, grid=0, fpe=0):
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(lib.rpk_exdot(x.numel(), _ptr(x), _ptr(y), _ptr(out), int(dots), ctypes.byref(L), _ptr(ws),
                          ws.numel(), _stream()), "rpk_exdot")
+    return out
+
+
+def exdot_noalloc(x, y, out, dots=EXACT, block=0, grid=0, fpe=0):
+    """<x, y> into the caller's 0-dim (or 1-element) float64 device tensor `out`
+    without any device allocation (the library's own scratch array); the same
+    bits as exdot().  Calls that overlap on one device race."""
+    lib = load()
+    x, y = _dev(x), _dev(y)
+    assert x.numel() == y.numel() and out.is_cuda and out.dtype == torch.float64 and out.numel() == 1
+    L = _launch(block, grid, fpe)
+    _check(lib.rpk_exdot_noalloc(x.numel(), _ptr(x), _ptr(y), _ptr(out), int(dots), ctypes.byref(L), _stream()),
+           "rpk_exdot_noalloc")
     return out
 
 

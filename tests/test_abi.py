@@ -151,3 +151,18 @@ def test_carry_budget_host_checks(lib):
     assert check([(1 << 31) - 1], 0, 0, 0) == 0                # the autotuner's candidates fit any n
     assert check([(1 << 31) - 1], 4096, 0, 0) == 0
     assert check([0], 4096, 0, 0) == 1 and check([1 << 31], 4096, 0, 0) == 1
+
+
+def test_noalloc_exdot_refuses_before_device_work(lib):
+    """The allocation-free exdot refuses what its scratch array cannot hold (and
+    bad arguments) before touching a device."""
+    P = ctypes.c_void_p
+
+    class Launch(ctypes.Structure):
+        _fields_ = [(f, ctypes.c_int32) for f in ("block", "grid", "fpe", "graph", "tile")]
+
+    lib.rpk_exdot_noalloc.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P]
+    assert lib.rpk_exdot_noalloc(1000, P(8), P(8), P(8), 0, ctypes.byref(Launch(512, 1625, 3, 0, 0)), None) == 1
+    assert lib.rpk_exdot_noalloc(1000, P(8), P(8), None, 0, None, None) == 1
+    assert lib.rpk_exdot_noalloc(1000, P(8), P(8), P(8), 2, None, None) == 1   # lightweight dots: rpk_fpedot
+    assert lib.rpk_exdot_noalloc(1 << 32, P(8), P(8), P(8), 0, None, None) == 1
