@@ -3,9 +3,12 @@
 One step = one complete exact PBiCGStab solve (Fig. 2, Jacobi, b = A*1, x0 = 0,
 tol 1e-10 on ||r||/||r0||) on one MI355X through the C ABI, inputs resident in
 HBM.  The reported value is iterations per second over the timed steps.  Beside
-it (outside the timed region): the plain FP64 twin and the pipelined variant on
-the same GPU, the per-kernel times of one instrumented solve (roofline of the
-dominant kernel), and the exact CPU oracle timed on a bounded sample.
+it (outside the timed region): the plain FP64 twin, the pipelined variant and
+PCG on the same GPU, the per-kernel times of one instrumented solve (roofline of
+the dominant kernel), the 16^3 Poisson, 96^3 convection-diffusion and 500k
+banded configurations (exact and plain), the batched and serving workloads,
+the 27-point 159^3 systems, and the exact CPU oracle with its plain FP64 twin
+timed on bounded samples of the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --profile   (fixed short workload for rocprofv3 counter passes)
@@ -76,32 +79,100 @@ def algorithmic_bytes(n, nnz):
     }
 
 
-def cpu_baseline(A, n_iter):
+def _lscpu_model():
+    """CPU model string as lscpu prints it (falls back to /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def _oracle_rate(oracle, A, b, variant, plain, k0, k1, tol):
+    """Steady-state iterations/s of the oracle: the time of a solve stopped at k1
+    iterations minus that of one stopped at k0, over k1 - k0 iterations (set-up,
+    first iterations and the exit residual cancel)."""
+    t = []
+    for m in (k0, k1):
+        t0 = time.perf_counter()
+        res = oracle.solve(*A, b, tol=tol, maxit=m, variant=variant, plain=plain)
+        t.append(time.perf_counter() - t0)
+        assert res["iters"] == m, res["status"]
+    return (k1 - k0) / max(t[1] - t[0], 1e-9), t[0] + t[1]
+
+
+def _oracle_solve_capped(oracle, A, b, variant, plain, tol, maxit, iters_expected, cap_s, gpu_x=None):
+    """A whole oracle solve when its predicted time fits cap_s, else the first
+    iterations that fit (reported as partial); iterations/s over the run."""
+    rate, spent = _oracle_rate(oracle, A, b, variant, plain, 1, 3, tol)
+    m = maxit if iters_expected / rate <= cap_s else max(5, int(cap_s * rate))
+    t0 = time.perf_counter()
+    res = oracle.solve(*A, b, tol=tol, maxit=m, variant=variant, plain=plain)
+    dt = time.perf_counter() - t0
+    out = {"iterations": res["iters"], "status": res["status"], "seconds": round(dt, 2),
+           "iters_per_s": round(res["iters"] / dt, 3), "complete": res["status"] != "NOT_CONVERGED" or m == maxit}
+    if gpu_x is not None and out["complete"] and not plain:
+        import numpy as np
+        out["x_equals_gpu"] = bool(np.array_equal(res["x"].view(np.uint64), gpu_x.view(np.uint64)))
+    return out, spent + dt
+
+
+def cpu_baseline(A, gpu_solves, cap_s=20.0):
+    """The oracle (exact) and the plain FP64 solver built from the same C source
+    with the dots and rows swapped, on the host cores of this machine.  Headline:
+    steady-state exact standard iterations/s on the 128^3 system (iterations 3..12,
+    all threads; 2..6 on one thread).  Beside it: whole solves of the 16^3 Poisson
+    (standard), the 96^3 convection-diffusion and the 500k banded systems
+    (pipelined), each capped at cap_s seconds of predicted time (partial beyond)."""
     import numpy as np
 
     import oracle
     oracle.load()
     b_host = oracle.exspmv(*A, np.ones(A[0].size - 1))
-    t0 = time.perf_counter()
-    res = oracle.solve(*A, b_host, tol=TOL, maxit=n_iter, variant=0)
-    dt = time.perf_counter() - t0
     cores = oracle.get_threads()
-    # the same oracle on one thread, over a shorter sample
+    total = 0.0
+    ips, spent = _oracle_rate(oracle, A, b_host, 0, False, 2, 12, TOL)
+    total += spent
+    log("  oracle 128^3 exact: %.3f iters/s on %d threads" % (ips, cores))
+    pips, spent = _oracle_rate(oracle, A, b_host, 0, True, 2, 12, TOL)
+    total += spent
     oracle.set_threads(1)
-    t1 = time.perf_counter()
-    res1 = oracle.solve(*A, b_host, tol=TOL, maxit=2, variant=0)
-    dt1 = time.perf_counter() - t1
-    oracle.set_threads(cores)
-    model = ""
     try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": res["iters"] / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d iterations (set-up and exit residual included) of the exact standard solve "
-                      "of the same 128^3 system; %.1f s" % (res["iters"], dt),
-            "one_core_iters_per_s": round(res1["iters"] / dt1, 3), "cpu_model": model}
+        ips1, spent = _oracle_rate(oracle, A, b_host, 0, False, 1, 6, TOL)
+        total += spent
+        pips1, spent = _oracle_rate(oracle, A, b_host, 0, True, 1, 6, TOL)
+        total += spent
+    finally:
+        oracle.set_threads(cores)
+    legs = {}
+    for name, (Ak, bk, variant, tol, maxit, it_gpu, x_gpu) in gpu_solves.items():
+        legs[name] = {}
+        for plain in (False, True):
+            r, spent = _oracle_solve_capped(oracle, Ak, bk, variant, plain, tol, maxit, it_gpu, cap_s, x_gpu)
+            legs[name]["plain" if plain else "exact"] = r
+            total += spent
+            log("  oracle %s %s: %s" % (name, "plain" if plain else "exact", r))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": round(ips, 3), "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": "iterations 3..12 of the exact standard solve of the same 128^3 system (time of a solve "
+                      "stopped at 12 minus one stopped at 2: set-up and exit residual excluded), %d threads"
+                      % cores,
+            "one_core_iters_per_s": round(ips1, 3),
+            "plain_fp64_iters_per_s": round(pips, 3), "plain_fp64_one_core_iters_per_s": round(pips1, 3),
+            "exact_over_plain_time_per_iteration": round(pips / ips, 2),
+            "host_cpus": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _lscpu_model(),
+            "configs": legs, "cpu_seconds_total": round(total, 1)}
 
 
 def profile_workload():
@@ -156,6 +227,63 @@ def profile_spmv_workload():
         print("%s %d: n %d nnz %d" % (gen.__name__, edge, M.n, M.nnz), flush=True)
         M.close()
     print("profile spmv workload done", flush=True)
+
+
+def config_legs(torch, rpk, inputs):
+    """The other single-GPU configurations, through the same C ABI, exact and
+    plain, whole solves from x0 = 0 (set-up and exit residual included):
+      - 7-point Poisson 16^3, x* ~ U(-1, 1) (seed 1), b = A x*, standard
+        PBiCGStab, tol 1e-8, maxit 500 -- latency-bound (an iteration moves
+        1.5 MB, which the caches hold): iterations/s only, no roofline claim;
+      - upwind convection-diffusion 96^3 (cell Peclet 0.5, 0.25, 0.125), b = A 1,
+        pipelined, tol 1e-9, maxit 10000;
+      - random banded n = 500,000 (20 entries per row within +-5000 of the
+        diagonal, seed 3), b = A 1, pipelined, tol 1e-9, maxit 10000.
+    Returns the report and, per configuration, what the CPU baseline needs (host
+    matrix and right-hand side, the GPU's exact iteration count and x)."""
+    import numpy as np
+    out, host = {}, {}
+    specs = [("poisson7_16^3_std", lambda: inputs.poisson7(16), lambda n: inputs.uniform(n, 1), rpk.STD, 1e-8,
+              500, 25, 40, False),
+             ("convdiff7_96^3_pipelined", lambda: inputs.convdiff7(96, (0.5, 0.25, 0.125)), np.ones,
+              rpk.PIPELINED, 1e-9, 10000, 42, 3, True),
+             ("random_banded_500k_pipelined", inputs.random_banded, np.ones, rpk.PIPELINED, 1e-9, 10000, 42, 20,
+              True)]
+    for name, gen, rhs, variant, tol, maxit, nvec, reps, hbm in specs:
+        A = gen()
+        M = rpk.Matrix(*A)
+        n, nnz = M.n, M.nnz
+        b = rpk.exspmv(M, torch.tensor(rhs(n), dtype=torch.float64, device="cuda"))
+        per_it = 2 * (12 * nnz + 4 * (n + 1)) + nvec * 8 * n
+        leg = {"n": n, "nnz": nnz, "tol": tol, "variant": "standard (Fig. 2)" if variant == rpk.STD
+               else "pipelined (Fig. 3)", "bytes_per_iteration": per_it,
+               "bound": "hbm" if hbm else "latency (an iteration's operands stay in the caches; no roofline claim)"}
+        for dots, dname in ((rpk.EXACT, "exact"), (rpk.PLAIN, "plain")):
+            x, info = rpk.solve(M, b, tol=tol, maxit=maxit, variant=variant, dots=dots)  # graphs captured
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it = 0
+            for _ in range(reps):
+                x, info = rpk.solve(M, b, tol=tol, maxit=maxit, variant=variant, dots=dots)
+                it += info["iters"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ips = it / dt
+            r = {"iters_per_s": round(ips, 1), "iterations": info["iters"], "status": info["status"],
+                 "ms_per_solve": round(1e3 * dt / reps, 3), "algorithmic_GBps": round(ips * per_it / 1e9, 1)}
+            if hbm:
+                r["roofline_frac"] = round(ips * per_it / 1e9 / HBM_PEAK_GBS, 4)
+            leg[dname] = r
+            if dots == rpk.EXACT:
+                host[name] = (A, b.cpu().numpy(), variant, tol, maxit, info["iters"], x.cpu().numpy())
+        leg["exact_over_plain_time_per_iteration"] = round(leg["plain"]["iters_per_s"] / leg["exact"]["iters_per_s"],
+                                                           3)
+        log("%s: exact %.1f iters/s (%d it), plain %.1f iters/s" % (name, leg["exact"]["iters_per_s"],
+                                                                   leg["exact"]["iterations"],
+                                                                   leg["plain"]["iters_per_s"]))
+        out[name] = leg
+        M.close()
+    return out, host
 
 
 def batched_leg(torch, rpk, inputs, reps=3):
@@ -260,14 +388,17 @@ def etype_leg(torch, rpk, inputs, reps=2):
     return out
 
 
-def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9, 0.5), seed=2024):
+def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.9, 0.5), seed=2024,
+                bins=12):
     """Open-loop Poisson arrivals of exact pipelined solves (tol 1e-9, maxit
     10000) on the request server; n log-uniform in [4096, 2.1M] (grid edge =
     round(n^(1/3)) clamped to [16, 128]), Poisson or convection-diffusion (Peclet
     U[0.1, 2]) from a seeded pool of matrices, right-hand side U(-1, 1) seeded by
     the request id.  Arrival rates: each of `loads` x the closed-loop saturation
     rate, one after the other on the same server (the first is reported at the
-    top level, the others under "at_<load>")."""
+    top level, the others under "at_<load>").  Afterwards the first measured
+    request to finish in each of `bins` log-spaced bins of n is solved again
+    alone and compared with its served result bit for bit."""
     import numpy as np
     rng = np.random.default_rng(seed)
     pool = []
@@ -299,10 +430,10 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9
     for t in ts:
         srv.wait(t)
     mu = 64 / (time.perf_counter() - t0)
-    check = None
+    lo_n, hi_n = np.log(4096), np.log(2.1e6)
+    samples = {}  # size bin -> (M, b, x as served, result)
 
     def open_loop(load, id0):
-        nonlocal check
         lam = load * mu
         gaps = rng.exponential(1.0 / lam, size=warm + n_req)
         arrivals = np.cumsum(gaps)
@@ -327,8 +458,9 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9
                     lat.append(res["latency_ms"])
                     qms.append(res["queue_ms"])
                     done_t.append(time.perf_counter() - t_start)
-                    if check is None and res["iters"] > 20:
-                        check = (M, b, x.clone(), res)
+                    k = int(min(bins - 1, max(0, (np.log(M.n) - lo_n) / (hi_n - lo_n) * bins)))
+                    if k not in samples:
+                        samples[k] = (M, b, x.clone(), res)
             time.sleep(0.0002)
         span = max(done_t) - arrivals[warm]
         lat = np.array(lat)
@@ -342,11 +474,12 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9
     phases = [open_loop(ld, 64 + k * (warm + n_req)) for k, ld in enumerate(loads)]
     st = srv.stats()
     srv.close()
-    same = None
-    if check is not None:
-        M, b, x, res = check
+    equal, sizes = 0, []
+    for k in sorted(samples):
+        M, b, x, res = samples[k]
         xa, ia = rpk.solve(M, b, tol=1e-9, maxit=10000, variant=rpk.PIPELINED)
-        same = ia["iters"] == res["iters"] and bool(torch.equal(xa, x))
+        equal += int(ia["iters"] == res["iters"] and ia["status"] == res["status"] and bool(torch.equal(xa, x)))
+        sizes.append(M.n)
     for M in pool:
         M.close()
     res = {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
@@ -355,7 +488,8 @@ def serving_leg(torch, rpk, inputs, n_req=400, warm=40, pool_size=48, loads=(0.9
     for ld, ph in zip(loads[1:], phases[1:]):
         res["at_%g" % ld] = ph
     res.update({"hbm_budget_GiB": 2, "bytes_peak_GiB": round(st["bytes_peak"] / 2 ** 30, 2),
-                "rounds": st["rounds"], "sampled_result_equals_alone": same})
+                "rounds": st["rounds"], "sampled_results_equal_alone": "%d/%d" % (equal, len(sizes)),
+                "sampled_n": sizes})
     return res
 
 
@@ -365,7 +499,6 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile", action="store_true", help="run the fixed counter-collection workload only")
     ap.add_argument("--profile-spmv", action="store_true", help="run the lone-SpMV counter-collection workload only")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched, serving and e-type legs")
@@ -488,6 +621,8 @@ def main():
         "phase_us": phase,
         "roofline": roofline,
     }
+    log("configurations 16^3, 96^3 convection-diffusion, 500k banded ...")
+    result["configs"], gpu_solves = config_legs(torch, rpk, inputs)
     if not args.no_batched:
         log("batched leg ...")
         result["batched"] = batched_leg(torch, rpk, inputs)
@@ -497,7 +632,7 @@ def main():
         result["etype27_159"] = etype_leg(torch, rpk, inputs)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(A, args.cpu_iters)
+        result["cpu_baseline"] = cpu_baseline(A, gpu_solves)
     else:
         result["cpu_baseline"] = None
     M.close()

@@ -48,6 +48,7 @@ def load():
     lib.or_jacobi.restype = ctypes.c_int
     lib.or_jacobi.argtypes = [ctypes.c_int64, P, P, P, P]
     lib.or_set_threads.argtypes = [ctypes.c_int]
+    lib.or_set_plain.argtypes = [ctypes.c_int]
     lib.or_get_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -99,9 +100,12 @@ def jacobi(row_ptr, col_idx, vals):
 
 
 def solve(row_ptr, col_idx, vals, b, x0=None, tol=1e-8, maxit=500, variant=STD,
-          record=False, record_xr=False):
+          record=False, record_xr=False, plain=False):
     """Run the exact solver.  Returns a dict with x, status, iters, tau0, tau,
-    true_res and optionally hist [maxit, HIST_W] and xr [maxit, 2, n]."""
+    true_res and optionally hist [maxit, HIST_W] and xr [maxit, 2, n].
+    plain=True runs the plain FP64 comparator instead (fma dot chains summed in
+    thread order, fma rows in CSR order; timed beside the exact solver, not a
+    reference for anything); its true_res is still exact."""
     rp, ci, v, b = _i32(row_ptr), _i32(col_idx), _f64(vals), _f64(b)
     n = rp.size - 1
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -109,9 +113,14 @@ def solve(row_ptr, col_idx, vals, b, x0=None, tol=1e-8, maxit=500, variant=STD,
     hist = np.zeros((m, HIST_W)) if record else None
     xr = np.zeros((m, 2, n)) if record_xr else None
     out = np.zeros(4)
-    st = load().or_solve(n, _p(rp), _p(ci), _p(v), _p(b), _p(x), float(tol), int(maxit),
-                         int(variant), _p(hist) if hist is not None else None,
-                         _p(xr) if xr is not None else None, _p(out))
+    lib = load()
+    lib.or_set_plain(1 if plain else 0)
+    try:
+        st = lib.or_solve(n, _p(rp), _p(ci), _p(v), _p(b), _p(x), float(tol), int(maxit),
+                          int(variant), _p(hist) if hist is not None else None,
+                          _p(xr) if xr is not None else None, _p(out))
+    finally:
+        lib.or_set_plain(0)
     res = {"x": x, "status": STATUS.get(st, st), "code": st, "iters": int(out[3]),
            "tau0": out[0], "tau": out[1], "true_res": out[2]}
     if record:

@@ -230,8 +230,50 @@ static int all_finite(int64_t n, const double *a) {
   return ok;
 }
 
+/*
+ * Plain FP64 comparator (the paper's "original" solver, Sec. 5.1), timed beside
+ * the exact oracle: with or_set_plain(1) the solver loops below take their dot
+ * products as per-thread fma chains summed in thread order, and their row sums
+ * as fma chains in CSR order, instead of the exact ones.  Not reproducible
+ * across thread counts; never used by the tests' exact pins.  The reported true
+ * residual stays exact.
+ */
+static int g_plain = 0;
+void or_set_plain(int on) { g_plain = on ? 1 : 0; }
+
+static double plain_dot(int64_t n, const double *x, const double *y) {
+  int T = omp_get_max_threads();
+  double *part = (double *)calloc((size_t)T, sizeof(double));
+  if (!part) abort();
+#pragma omp parallel
+  {
+    int t = omp_get_thread_num(), nt = omp_get_num_threads();
+    int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+    double acc = 0.0;
+    for (int64_t i = lo; i < hi; i++) acc = fma(x[i], y[i], acc);
+    part[t] = acc;
+  }
+  double r = 0.0;
+  for (int t = 0; t < T; t++) r += part[t];
+  free(part);
+  return r;
+}
+
+static double dot(int64_t n, const double *x, const double *y) {
+  return g_plain ? plain_dot(n, x, y) : or_exdot(n, x, y);
+}
+
 static void spmv(const or_mat *A, const double *x, double *y) {
-  or_exspmv(A->n, A->rp, A->ci, A->v, x, y);
+  if (!g_plain) {
+    or_exspmv(A->n, A->rp, A->ci, A->v, x, y);
+    return;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < A->n; i++) {
+    double acc = 0.0;
+    for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) acc = fma(A->v[k], x[A->ci[k]], acc);
+    y[i] = acc;
+  }
 }
 
 static void record_xr(double *xr_hist, int64_t n, int j, const double *x, const double *r) {
@@ -242,7 +284,7 @@ static void record_xr(double *xr_hist, int64_t n, int j, const double *x, const 
 
 /* true residual norm RN(sqrt(exdot(e, e))), e_i = RN(b_i - (A x)_i) */
 static double true_residual(const or_mat *A, const double *b, const double *x, double *tmp) {
-  spmv(A, x, tmp);
+  or_exspmv(A->n, A->rp, A->ci, A->v, x, tmp);
   for (int64_t i = 0; i < A->n; i++) tmp[i] = b[i] - tmp[i];
   return sqrt(or_exdot(A->n, tmp, tmp));
 }
@@ -268,7 +310,7 @@ static int solve_std(const or_mat *A, const double *dinv, const double *b, doubl
   for (int64_t i = 0; i < n; i++) r[i] = b[i] - s[i];
   memcpy(r0, r, n * 8);
   memcpy(p, r, n * 8);
-  rho = or_exdot(n, r0, r);
+  rho = dot(n, r0, r);
   if (isnan(rho)) { status = OR_ERR_NONFINITE; tau0 = tau = NAN; goto done; }
   tau0 = sqrt(rho);
   tau = tau0;
@@ -284,7 +326,7 @@ static int solve_std(const or_mat *A, const double *dinv, const double *b, doubl
     /* S2 */
     spmv(A, ph, s);
     /* S3 */
-    double sigma = or_exdot(n, r0, s);
+    double sigma = dot(n, r0, s);
     if (h) h[0] = sigma;
     if (isnan(sigma)) { status = OR_ERR_NONFINITE; break; }
     if (sigma == 0.0) { status = OR_BREAKDOWN; break; }
@@ -299,7 +341,7 @@ static int solve_std(const or_mat *A, const double *dinv, const double *b, doubl
     /* S6 */
     spmv(A, qh, y);
     /* S7 */
-    double theta = or_exdot(n, q, y), phi = or_exdot(n, y, y);
+    double theta = dot(n, q, y), phi = dot(n, y, y);
     if (h) { h[2] = theta; h[3] = phi; }
     if (isnan(theta) || isnan(phi)) { status = OR_ERR_NONFINITE; break; }
     double omega = (phi == 0.0) ? 0.0 : theta / phi;
@@ -311,7 +353,7 @@ static int solve_std(const or_mat *A, const double *dinv, const double *b, doubl
       r[i] = fma(-omega, y[i], q[i]);
     }
     /* S10, S11 */
-    double rho_new = or_exdot(n, r0, r), gamma = or_exdot(n, r, r);
+    double rho_new = dot(n, r0, r), gamma = dot(n, r, r);
     if (h) { h[5] = rho_new; h[6] = gamma; }
     record_xr(xr_hist, n, j, x, r);
     j++;
@@ -356,7 +398,7 @@ static int solve_pipe(const or_mat *A, const double *dinv, const double *b, doub
   spmv(A, x, t);
   for (int64_t i = 0; i < n; i++) r[i] = b[i] - t[i];
   memcpy(r0, r, n * 8);
-  rho = or_exdot(n, r0, r);
+  rho = dot(n, r0, r);
   if (isnan(rho)) { status = OR_ERR_NONFINITE; tau0 = tau = NAN; goto done; }
   tau0 = sqrt(rho);
   tau = tau0;
@@ -366,7 +408,7 @@ static int solve_pipe(const or_mat *A, const double *dinv, const double *b, doub
   spmv(A, rh, w);
   for (int64_t i = 0; i < n; i++) wh[i] = dinv[i] * w[i];
   spmv(A, wh, t);
-  double mu = or_exdot(n, r0, w);
+  double mu = dot(n, r0, w);
   if (isnan(mu)) { status = OR_ERR_NONFINITE; goto done; }
   if (mu == 0.0) { status = OR_BREAKDOWN; goto done; }
   alpha = rho / mu;
@@ -386,7 +428,7 @@ static int solve_pipe(const or_mat *A, const double *dinv, const double *b, doub
       y[i] = fma(-alpha, z[i], w[i]);                      /* S7 */
     }
     /* S8 */
-    double theta = or_exdot(n, q, y), phi = or_exdot(n, y, y);
+    double theta = dot(n, q, y), phi = dot(n, y, y);
     if (h) { h[0] = theta; h[1] = phi; }
     /* S9, S10 */
 #pragma omp parallel for schedule(static)
@@ -404,8 +446,8 @@ static int solve_pipe(const or_mat *A, const double *dinv, const double *b, doub
       w[i] = fma(-omega, fma(-alpha, v[i], t[i]), y[i]);   /* S15 */
     }
     /* S16 */
-    double rho_new = or_exdot(n, r0, r), mu_new = or_exdot(n, r0, w),
-           vs = or_exdot(n, r0, s), zeta = or_exdot(n, r0, z), gamma = or_exdot(n, r, r);
+    double rho_new = dot(n, r0, r), mu_new = dot(n, r0, w),
+           vs = dot(n, r0, s), zeta = dot(n, r0, z), gamma = dot(n, r, r);
     if (h) { h[3] = rho_new; h[4] = mu_new; h[5] = vs; h[6] = zeta; h[7] = gamma; }
     record_xr(xr_hist, n, j, x, r);
     /* S17, S18 */
@@ -464,9 +506,9 @@ static int solve_pcg(const or_mat *A, const double *dinv, const double *b, doubl
     y[i] = dinv[i] * r[i];
     p[i] = y[i];
   }
-  beta = or_exdot(n, y, r);
+  beta = dot(n, y, r);
   {
-    double gamma = or_exdot(n, r, r);
+    double gamma = dot(n, r, r);
     if (isnan(beta) || isnan(gamma)) { status = OR_ERR_NONFINITE; tau0 = tau = NAN; goto done; }
     tau0 = sqrt(gamma);
   }
@@ -480,7 +522,7 @@ static int solve_pcg(const or_mat *A, const double *dinv, const double *b, doubl
     /* S1 */
     spmv(A, p, d);
     /* S2 */
-    double pd = or_exdot(n, p, d);
+    double pd = dot(n, p, d);
     if (h) h[0] = pd;
     if (isnan(pd)) { status = OR_ERR_NONFINITE; break; }
     if (pd == 0.0) { status = OR_BREAKDOWN; break; }
@@ -495,8 +537,8 @@ static int solve_pcg(const or_mat *A, const double *dinv, const double *b, doubl
     }
     /* S6, S7, S8 */
     double alpha = beta;
-    beta = or_exdot(n, y, r);
-    double gamma = or_exdot(n, r, r);
+    beta = dot(n, y, r);
+    double gamma = dot(n, r, r);
     if (h) { h[2] = beta; h[3] = gamma; }
     record_xr(xr_hist, n, j, x, r);
     j++;

@@ -311,3 +311,20 @@ def test_true_residual_closed_forms(orc, variant):
     for v in b.tolist():
         plain = fracref.fma(v, v, plain)
     assert math.sqrt(plain) == 1.0
+
+
+def test_plain_comparator_converges_and_switches_back(orc):
+    """The plain FP64 CPU solver timed beside the oracle (same source, dots and
+    rows swapped) converges on the 16^3 problem for every variant, differs from
+    the exact solver in its iterates, and leaves the exact solver unchanged."""
+    A = inputs.poisson7(16)
+    xs = inputs.uniform(16 ** 3, 1)
+    b = orc.exspmv(*A, xs)
+    for variant in (0, 1, 2):
+        ex = orc.solve(*A, b, tol=1e-8, maxit=500, variant=variant)
+        pl = orc.solve(*A, b, tol=1e-8, maxit=500, variant=variant, plain=True)
+        again = orc.solve(*A, b, tol=1e-8, maxit=500, variant=variant)
+        assert pl["status"] == "OK" and abs(pl["iters"] - ex["iters"]) <= 3
+        assert np.max(np.abs(pl["x"] - xs)) < 1e-5
+        assert pl["x"].tobytes() != ex["x"].tobytes()
+        assert again["x"].tobytes() == ex["x"].tobytes() and again["iters"] == ex["iters"]
