@@ -37,6 +37,8 @@ struct Batch {
   const int* count;  // [0] number of tiles, [1] number of systems in `order`
   int far;           // the batch's vectors do not fit in the Infinity Cache: the host
                      // launches the Far / Mid instantiations (streamed vectors)
+  int unif;          // every system's Jacobi vector is uniform (Csr::unif): the host
+                     // launches the Unif instantiations of the standard loop
 };
 
 // The tile of entry t, uniform over the workgroup: kept (and so the address of
@@ -135,46 +137,46 @@ __global__ void __launch_bounds__(1024) kb_std_init(Batch B) {
   });
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) kb_std_A(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_A_body<Far>(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { std_A_body<Far, Unif>(D.A, D.V, R); });
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_std_B(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   tile_loop<N, 1, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_B_body<N>(D.A, D.V, D.red, R, rec, s);
+    std_B_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) kb_std_C(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_C_body<Far>(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { std_C_body<Far, Unif>(D.A, D.V, R); });
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_std_D(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_D_body<N>(D.A, D.V, D.red, R, rec, s);
+    std_D_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) kb_std_E(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_E_body<N, Far>(D.A, D.V, D.red, R, rec, s);
+    std_E_body<N, Far, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 

@@ -215,8 +215,13 @@ Batch batch_of(const Ctx& c) {
   B.order = (const int*)(c.ws + c.L.order);
   B.tiles = (const Tile*)(c.ws + c.L.tiles);
   int64_t rows = 0;
-  for (int64_t v : c.n) rows += v;
-  B.far = rows_stream_far(rows, c.o->variant) ? 1 : 0;
+  bool unif = true;
+  for (int k = 0; k < c.ns; ++k) {
+    rows += c.n[k];
+    unif = unif && c.A[k]->unif != 0;
+  }
+  B.far = rows_stream_far(rows, c.o->variant, unif) ? 1 : 0;
+  B.unif = unif ? 1 : 0;
   return B;
 }
 

@@ -23,6 +23,8 @@ struct rpk_matrix {
   double* sval = nullptr;
   long long sell_entries = 0;      // entries of the SELL copy, padding included
   int cert = 0;                    // rows of wide slices try the certified sum (see Csr)
+  int unif = 0;                    // every dinv_i has the bits of du (see Csr)
+  double du = 0.0;
 };
 
 namespace rpkhost {
@@ -57,7 +59,9 @@ inline bool records_fit(int64_t records, int64_t lanes, int fpe) {
   return records * (lanes * (int64_t)fpe + 1) <= kCarryChunks;
 }
 
-inline Csr csr_of(const rpk_matrix* A) { return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert, 0}; }
+inline Csr csr_of(const rpk_matrix* A) {
+  return Csr{A->sptr, A->scol, A->sval, A->dinv, (int)A->n, A->cert, 0, A->unif, A->du};
+}
 
 inline int nvec_of(int variant) { return variant == RPK_STD ? 8 : variant == RPK_PCG ? 4 : 16; }
 
@@ -78,22 +82,28 @@ inline int keep_slices(const rpk_matrix* A, int nvec) {
   return (int)((double)A->nslices * (room / sell));
 }
 
+// Vectors one standard iteration touches: its eight work vectors, x and the
+// Jacobi vector; with a uniform Jacobi vector p^ and q^ are never stored and
+// dinv is a scalar, which leaves seven.
+inline int std_vectors(bool unif) { return unif ? 7 : nvec_of(RPK_STD) + 2; }
+
 // Whether a solve streams vectors past the Infinity Cache beyond what it always
-// does (Vecs::far): the standard loop when its ten vectors do not fit in nine
-// tenths of the cache, the pipelined loop when the eleven it otherwise keeps
-// do not.
-// A batch of systems decides the same way on its total number of rows.
-inline bool rows_stream_far(int64_t rows, int variant) {
-  const int kept = variant == RPK_STD ? nvec_of(RPK_STD) + 2 : variant == RPK_PIPELINED ? 11 : 0;
+// does (Vecs::far): the standard loop when the vectors it touches do not fit in
+// nine tenths of the cache, the pipelined loop when the eleven it otherwise
+// keeps do not.  A batch of systems decides the same way on its total number of
+// rows (unif: every system's Jacobi vector is uniform).
+inline bool rows_stream_far(int64_t rows, int variant, bool unif) {
+  const int kept = variant == RPK_STD ? std_vectors(unif) : variant == RPK_PIPELINED ? 11 : 0;
   return kept > 0 && (double)kept * (double)rows * 8.0 > 0.9 * kInfinityCacheBytes;
 }
-inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_far(A->n, variant); }
+inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_far(A->n, variant, A->unif != 0); }
 
-// Vectors of one iteration that stay in the Infinity Cache (the work vectors,
-// x and the Jacobi vector, less those streamed past it)
-inline int cached_vectors(int variant, bool far) {
+// Vectors of one iteration that stay in the Infinity Cache (those it touches,
+// less those streamed past it: x, p, r0 and dinv in the standard loop, x and r0
+// with a uniform Jacobi vector)
+inline int cached_vectors(int variant, bool far, bool unif) {
   if (variant == RPK_PIPELINED) return far ? 4 : 11;
-  if (variant == RPK_STD) return far ? 6 : nvec_of(RPK_STD) + 2;
+  if (variant == RPK_STD) return std_vectors(unif) - (far ? (unif ? 2 : 4) : 0);
   return nvec_of(variant) + 2;
 }
 

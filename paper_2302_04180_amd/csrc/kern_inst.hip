@@ -39,15 +39,33 @@ rpk_status Kern<N>::resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
 template <int N>
 rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
   if (variant == RPK_STD) {
-    const bool far = V.far != 0;  // x, p, r0 and the Jacobi vector streamed past the Infinity Cache
+    // far: vectors streamed past the Infinity Cache (x, p, r0 and the Jacobi
+    // vector; x and r0 in the Unif path); A.unif: p^ and q^ formed where read
+    const bool far = V.far != 0;
+    const size_t s1 = shm_bytes(N, 1, true, B), s2 = shm_bytes(N, 2, true, B), s2e = shm_bytes(N, 2, false, B);
+    if (A.unif) {
+      switch (ph) {
+        case 0: return launch(k_std_A<N, false, true>, G, B, 0, s, A, V);
+        case 1: return launch(k_std_B<N, true>, G, B, s1, s, A, V, red);
+        case 2: return launch(k_std_C<N, false, true>, G, B, 0, s, A, V);
+        case 3: return launch(k_std_D<N, true>, G, B, s2, s, A, V, red);
+        default:
+          return far ? launch(k_std_E<N, true, true>, G, B, s2e, s, A, V, red)
+                     : launch(k_std_E<N, false, true>, G, B, s2e, s, A, V, red);
+      }
+    }
     switch (ph) {
-      case 0: return far ? launch(k_std_A<N, true>, G, B, 0, s, A, V) : launch(k_std_A<N, false>, G, B, 0, s, A, V);
-      case 1: return launch(k_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 2: return far ? launch(k_std_C<N, true>, G, B, 0, s, A, V) : launch(k_std_C<N, false>, G, B, 0, s, A, V);
-      case 3: return launch(k_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
+      case 0:
+        return far ? launch(k_std_A<N, true, false>, G, B, 0, s, A, V)
+                   : launch(k_std_A<N, false, false>, G, B, 0, s, A, V);
+      case 1: return launch(k_std_B<N, false>, G, B, s1, s, A, V, red);
+      case 2:
+        return far ? launch(k_std_C<N, true, false>, G, B, 0, s, A, V)
+                   : launch(k_std_C<N, false, false>, G, B, 0, s, A, V);
+      case 3: return launch(k_std_D<N, false>, G, B, s2, s, A, V, red);
       default:
-        return far ? launch(k_std_E<N, true>, G, B, shm_bytes(N, 2, false, B), s, A, V, red)
-                   : launch(k_std_E<N, false>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+        return far ? launch(k_std_E<N, true, false>, G, B, s2e, s, A, V, red)
+                   : launch(k_std_E<N, false, false>, G, B, s2e, s, A, V, red);
     }
   }
   if (variant == RPK_PCG) {
@@ -99,14 +117,28 @@ template <int N>
 rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_t s, Batch b) {
   (void)Gf;
   if (variant == RPK_STD) {
+    const size_t s1 = shm_bytes(N, 1, true, B), s2 = shm_bytes(N, 2, true, B), s2e = shm_bytes(N, 2, false, B);
+    if (b.unif) {
+      switch (ph) {
+        case 0: return launch(kb_std_A<N, false, true>, G, B, 0, s, b);
+        case 1: return launch(kb_std_B<N, true>, G, B, s1, s, b);
+        case 2: return launch(kb_std_C<N, false, true>, G, B, 0, s, b);
+        case 3: return launch(kb_std_D<N, true>, G, B, s2, s, b);
+        default:
+          return b.far ? launch(kb_std_E<N, true, true>, G, B, s2e, s, b)
+                       : launch(kb_std_E<N, false, true>, G, B, s2e, s, b);
+      }
+    }
     switch (ph) {
-      case 0: return b.far ? launch(kb_std_A<N, true>, G, B, 0, s, b) : launch(kb_std_A<N, false>, G, B, 0, s, b);
-      case 1: return launch(kb_std_B<N>, G, B, shm_bytes(N, 1, true, B), s, b);
-      case 2: return b.far ? launch(kb_std_C<N, true>, G, B, 0, s, b) : launch(kb_std_C<N, false>, G, B, 0, s, b);
-      case 3: return launch(kb_std_D<N>, G, B, shm_bytes(N, 2, true, B), s, b);
+      case 0:
+        return b.far ? launch(kb_std_A<N, true, false>, G, B, 0, s, b) : launch(kb_std_A<N, false, false>, G, B, 0, s, b);
+      case 1: return launch(kb_std_B<N, false>, G, B, s1, s, b);
+      case 2:
+        return b.far ? launch(kb_std_C<N, true, false>, G, B, 0, s, b) : launch(kb_std_C<N, false, false>, G, B, 0, s, b);
+      case 3: return launch(kb_std_D<N, false>, G, B, s2, s, b);
       default:
-        return b.far ? launch(kb_std_E<N, true>, G, B, shm_bytes(N, 2, false, B), s, b)
-                     : launch(kb_std_E<N, false>, G, B, shm_bytes(N, 2, false, B), s, b);
+        return b.far ? launch(kb_std_E<N, true, false>, G, B, s2e, s, b)
+                     : launch(kb_std_E<N, false, false>, G, B, s2e, s, b);
     }
   }
   if (variant == RPK_PCG) {

@@ -58,6 +58,11 @@ struct Csr {
   // in the Infinity Cache for the next SpMV; the rest with non-temporal loads,
   // which leave the cache to the vectors (the same values either way)
   int keep;
+  // every dinv_i has the same bits, du (decided at creation): M^-1 is then the
+  // scalar du, and a preconditioned vector RN(dinv_i v_i) = RN(du v_i) can be
+  // formed where it is read instead of being stored (the same values either way)
+  int unif;
+  double du;
 };
 
 // Device-resident solver state (one per solve, in the caller's workspace).
@@ -256,10 +261,25 @@ struct Dot<LW8> {
 // ---------------------------------------------------------------------------
 // CSR rows
 // ---------------------------------------------------------------------------
-// Gathers: the value the SpMV multiplies a_ij by, as a function of the column.
+// Gathers: the value the SpMV multiplies a_ij by, as a function of the column,
+// in two parts: load(c), the memory access, and fin(v), arithmetic on the loaded
+// value.  The row loops issue the loads of a batch of entries under their
+// column guards first and apply fin afterwards, outside the guards, so that no
+// load waits for the one before it.
 struct GatherX {  // plain vector
   const double* __restrict__ x;
+  __device__ __forceinline__ double load(int c) const { return x[c]; }
+  __device__ __forceinline__ double fin(double v) const { return v; }
   __device__ __forceinline__ double operator()(int c) const { return x[c]; }
+};
+// M^-1 v for a uniform Jacobi vector (Csr::unif), formed at the gather:
+// RN(du * v_c), the value a stored copy would hold.
+struct GatherScaled {
+  double du;
+  const double* __restrict__ v;
+  __device__ __forceinline__ double load(int c) const { return v[c]; }
+  __device__ __forceinline__ double fin(double x) const { return du * x; }
+  __device__ __forceinline__ double operator()(int c) const { return du * v[c]; }
 };
 
 // A matrix entry or column index: non-temporal (NT) or ordinary load.
@@ -290,7 +310,9 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
       c[u] = in ? ld_entry<NT>(scol + (size_t)(j0 + u) * 64) : -1;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.load(c[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.fin(b[u]) : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double p = a[u] * b[u];
@@ -336,7 +358,9 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
       c[u] = in ? ld_entry<NT>(scol + (size_t)(j0 + u) * 64) : -1;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.load(c[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.fin(b[u]) : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double p = a[u] * b[u];
@@ -435,7 +459,9 @@ __device__ __forceinline__ double rows_wave_nt(const Csr& A, const Gth& gx, int 
         c[u] = in ? ld_entry<NT>(sc + (size_t)(j0 + u) * 64) : -1;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx(c[u]) : 0.0;
+      for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.load(c[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.fin(b[u]) : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (c[u] >= 0) acc = fma(a[u], b[u], acc);
@@ -479,6 +505,16 @@ template <int N>
 __device__ __forceinline__ double rows_wave(const Csr& A, const double* __restrict__ x, int row, bool valid,
                                             long long* wsa_block) {
   return rows_wave_g<N>(A, GatherX{x}, row, valid, wsa_block);
+}
+
+// (A M^-1 v)_row: gathers the stored preconditioned vector vh, or, for a uniform
+// Jacobi vector (Unif), v itself scaled at the gather (same values)
+template <int N, bool Unif>
+__device__ __forceinline__ double rows_wave_hat(const Csr& A, const double* __restrict__ v,
+                                                const double* __restrict__ vh, int row, bool valid,
+                                                long long* wsa_block) {
+  if constexpr (Unif) return rows_wave_g<N>(A, GatherScaled{A.du, v}, row, valid, wsa_block);
+  else return rows_wave_g<N>(A, GatherX{vh}, row, valid, wsa_block);
 }
 
 // ---------------------------------------------------------------------------

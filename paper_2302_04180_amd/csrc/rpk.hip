@@ -285,6 +285,7 @@ static rpk_status build_sell(rpk_matrix* A, hipStream_t s) {
 // pseudo-random vector and take the cheaper form (bound only, then with the
 // exactness check) under which at most one slice in eight has a row it cannot
 // certify; neither, when both fail more often (results are the same either way).
+// Also whether the Jacobi vector is uniform (Csr::unif).
 static rpk_status probe_cert(rpk_matrix* A, hipStream_t s) {
   A->cert = 0;
   double* x = nullptr;
@@ -305,6 +306,17 @@ static rpk_status probe_cert(rpk_matrix* A, hipStream_t s) {
         hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
     A->cert = (h[2] > 0 && 8ull * h[0] <= h[2]) ? 1 : (h[2] > 0 && 8ull * h[1] <= h[2]) ? 2 : 0;
+    // a uniform Jacobi vector (every dinv_i with the bits of dinv_0)
+    if (hipMemsetAsync(counts, 0, sizeof(unsigned), s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    hipLaunchKernelGGL(k_dinv_uniform, dim3((unsigned)((A->n + 255) / 256)), dim3(256), 0, s, A->dinv, (int)A->n,
+                       counts);
+    double d0 = 0.0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h, counts, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&d0, A->dinv, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
+    A->unif = h[0] == 0u ? 1 : 0;
+    A->du = d0;
   } while (0);
   (void)hipFree(x);
   (void)hipFree(counts);
@@ -518,7 +530,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   Vecs V = carve_vecs(w, l, A->n, variant, x, b, o);
   Csr Ac = csr_of(A);
   V.far = streams_far(A, variant) ? 1 : 0;
-  Ac.keep = keep_slices(A, cached_vectors(variant, V.far != 0));
+  Ac.keep = keep_slices(A, cached_vectors(variant, V.far != 0, A->unif != 0));
 
   const bool resume = o->resume != 0;
   // reduction scratch to zero; caller-visible histories to zero (not when resuming)

@@ -117,7 +117,8 @@ struct rpk_server {
   State* h_states = nullptr; // pinned
   std::vector<Req*> slots;
   std::vector<int> free_slots;
-  int view_far[NVIEW] = {};  // per view: its systems' vectors do not fit in the Infinity Cache
+  int view_far[NVIEW] = {};   // per view: its systems' vectors do not fit in the Infinity Cache
+  int view_unif[NVIEW] = {};  // per view: every system's Jacobi vector is uniform
 
   mutable std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -160,6 +161,7 @@ Batch view(const rpk_server* S, int v) {
   B.order = (const int*)(S->hdr + S->off_order) + (size_t)v * S->o.max_slots;
   B.tiles = (const Tile*)(S->hdr + S->off_tiles) + (size_t)v * S->tile_cap;
   B.far = S->view_far[v];
+  B.unif = S->view_unif[v];
   return B;
 }
 
@@ -168,11 +170,14 @@ Batch view(const rpk_server* S, int v) {
 rpk_status set_view(rpk_server* S, int v, const std::vector<int>& slots_v, int* ntiles) {
   std::vector<int64_t> n;
   int64_t rows = 0;
+  bool unif = true;
   for (int k : slots_v) {
     n.push_back(S->slots[k]->n);
     rows += S->slots[k]->n;
+    unif = unif && S->slots[k]->A->unif != 0;
   }
-  S->view_far[v] = rows_stream_far(rows, S->o.solve.variant) ? 1 : 0;
+  S->view_far[v] = rows_stream_far(rows, S->o.solve.variant, unif) ? 1 : 0;
+  S->view_unif[v] = unif ? 1 : 0;
   Plan p;
   if (!slots_v.empty()) p = make_plan(n, S->tile, &slots_v);
   if ((int64_t)p.tiles.size() > S->tile_cap) {

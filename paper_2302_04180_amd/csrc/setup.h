@@ -42,6 +42,13 @@ __global__ void k_setup_rows(const int* rp, const int* ci, const double* v, int 
   if (fl) atomicOr(flags, fl);
 }
 
+// *differ = 1 when some dinv_i does not have the bits of dinv_0 (Csr::unif)
+__global__ void k_dinv_uniform(const double* dinv, int n, unsigned* differ) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (__double_as_longlong(dinv[i]) != __double_as_longlong(dinv[0])) atomicOr(differ, 1u);
+}
+
 // SELL-64 construction (see Csr): width of each 64-row slice ...
 __global__ void k_slice_width(const int* rp, int n, int nslices, int* width) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;

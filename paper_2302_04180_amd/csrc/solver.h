@@ -5,7 +5,12 @@
 // scalar step (kernels.h, block_publish_last), so no separate finishing kernel
 // and no grid-wide fence is needed.  Recomputing p^ / q^ inside the SpMV
 // gathers instead of storing them was measured slower: it multiplies the
-// gathered vectors by 3-4.
+// gathered vectors by 3-4 (gathering p and dinv alone, 2, still cost more than
+// the stores it saves).  Where the Jacobi vector is uniform (Csr::unif) they are
+// formed where they are read, RN(du v_i) at the gathers and in E, and never
+// stored: 19 vector streams per iteration instead of 25.  The host picks that
+// path (the Unif instantiations) per launch: for a single solve from the
+// matrix, for a batch when every system's Jacobi vector is uniform.
 //   A: S12 (from the second iteration on) + S1
 //   B: S2 SpMV (gathers p^) + S3                  -> last workgroup: alpha
 //   C: S4 + S5
@@ -367,12 +372,25 @@ __device__ __forceinline__ void st_v(double* p, double v) {
 __device__ __forceinline__ double ld_far(const double* p) { return ld_v<true>(p); }
 __device__ __forceinline__ void st_far(double* p, double v) { st_v<true>(p, v); }
 
-// A: S12 (iterations after the first) and S1
-template <bool Far = false>
+// A: S12 (iterations after the first) and S1 (not stored for a uniform Jacobi
+// vector: B and E form p^ themselves)
+template <bool Far, bool Unif>
 __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R) {
   const State* st = V.st;
   const bool upd = st->iter > 0;
   const double beta = st->beta, omega = st->omega;
+  if constexpr (Unif) {
+    if (!upd) return;  // p = r0 from the set-up
+    for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+      const int i1 = i0 + blockDim.x;
+      const bool two = i1 < R.hi;
+      const int j1 = two ? i1 : i0;
+      const double p0 = V.p[i0], p1 = V.p[j1], s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
+      V.p[i0] = fma(beta, fma(-omega, s0, p0), r0);  // S12
+      if (two) V.p[i1] = fma(beta, fma(-omega, s1, p1), r1);
+    }
+    return;
+  }
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
     const bool two = i1 < R.hi;
@@ -403,7 +421,7 @@ __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R)
 }
 
 // B: S2 + S3 partial
-template <int N>
+template <int N, bool Unif>
 __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s) {
   Dot<N> d[1];
@@ -412,7 +430,7 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
     const int i = base + threadIdx.x;
     const bool ok = i < R.hi;
     const double r0 = ok ? V.r0[i] : 0.0;
-    const double si = rows_wave<N>(A, V.ph, i, ok, s.wsa);
+    const double si = rows_wave_hat<N, Unif>(A, V.p, V.ph, i, ok, s.wsa);
     if (ok) {
       V.s[i] = si;
       d[0].add(r0, si, s.sa, &s.flag[0]);
@@ -421,10 +439,21 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
   publish_step<N, 1, FIN_ALPHA>(d, s, V, red, rec);
 }
 
-// C: S4 + S5
-template <bool Far = false>
+// C: S4 + S5 (S5 not stored for a uniform Jacobi vector: D and E form q^)
+template <bool Far, bool Unif>
 __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R) {
   const double alpha = V.st->alpha;
+  if constexpr (Unif) {
+    for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+      const int i1 = i0 + blockDim.x;
+      const bool two = i1 < R.hi;
+      const int j1 = two ? i1 : i0;
+      const double s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
+      V.q[i0] = fma(-alpha, s0, r0);  // S4
+      if (two) V.q[i1] = fma(-alpha, s1, r1);
+    }
+    return;
+  }
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
     const bool two = i1 < R.hi;
@@ -443,7 +472,7 @@ __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R)
 }
 
 // D: S6 + S7 partials
-template <int N>
+template <int N, bool Unif>
 __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s) {
   Dot<N> d[2];
@@ -453,7 +482,7 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
     const int i = base + threadIdx.x;
     const bool ok = i < R.hi;
     const double q = ok ? V.q[i] : 0.0;
-    const double yi = rows_wave<N>(A, V.qh, i, ok, s.wsa);
+    const double yi = rows_wave_hat<N, Unif>(A, V.q, V.qh, i, ok, s.wsa);
     if (ok) {
       V.y[i] = yi;
       d[0].add(q, yi, s.sa, &s.flag[0]);
@@ -463,16 +492,13 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
   publish_step<N, 2, FIN_OMEGA>(d, s, V, red, rec);
 }
 
-// E: S8 + S9 + S10/S11 partials
-template <int N, bool Far = false>
-__device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
-                                           const Shm<N>& s) {
+// E: S8 + S9 + S10/S11 partials.  Unif: p^ = RN(du p) and q^ = RN(du q) are
+// formed here from p and q (q is read for S9 anyway).
+template <int N, bool Far, bool Unif>
+__device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R, Dot<N> (&d)[2], const Shm<N>& s) {
   const State* st = V.st;
-  const double alpha = st->alpha, omega = st->omega;
+  const double alpha = st->alpha, omega = st->omega, du = A.du;
   const int iter = st->iter;
-  Dot<N> d[2];
-  d[0].zero();
-  d[1].zero();
   // two rows per step, every load issued before any store
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
@@ -481,8 +507,12 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int i = u ? (two ? i1 : i0) : i0;
-      qh[u] = V.qh[i];
-      ph[u] = V.ph[i];
+      if constexpr (Unif) {
+        ph[u] = V.p[i];
+      } else {
+        qh[u] = V.qh[i];
+        ph[u] = V.ph[i];
+      }
       xo[u] = ld_v<Far>(&V.x[i]);
       y[u] = V.y[i];
       q[u] = V.q[i];
@@ -492,6 +522,10 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
     for (int u = 0; u < 2; ++u) {
       if (u == 1 && !two) break;
       const int i = u ? i1 : i0;
+      if constexpr (Unif) {
+        ph[u] = du * ph[u];  // S1
+        qh[u] = du * q[u];   // S5
+      }
       const double x = fma(omega, qh[u], fma(alpha, ph[u], xo[u]));  // S8
       const double r = fma(-omega, y[u], q[u]);                       // S9
       st_v<Far>(&V.x[i], x);
@@ -501,6 +535,15 @@ __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Re
       d[1].add(r, r, s.sa + SA_D, &s.flag[1]);                        // S11
     }
   }
+}
+
+template <int N, bool Far, bool Unif>
+__device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
+                                           const Shm<N>& s) {
+  Dot<N> d[2];
+  d[0].zero();
+  d[1].zero();
+  std_E_rows<N, Far, Unif>(A, V, R, d, s);
   publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
 }
 
@@ -729,43 +772,43 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
   std_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
   if (V.st->done) return;
-  std_A_body<Far>(A, V, my_rows(A.n));
+  std_A_body<Far, Unif>(A, V, my_rows(A.n));
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   shm_init(s, 1);
-  std_B_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_B_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
   if (V.st->done) return;
-  std_C_body<Far>(A, V, my_rows(A.n));
+  std_C_body<Far, Unif>(A, V, my_rows(A.n));
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   shm_init(s, 2);
-  std_D_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_D_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N, bool Far>
+template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   shm_init(s, 2);
-  std_E_body<N, Far>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_E_body<N, Far, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N>

@@ -56,6 +56,17 @@ def poisson7(N):
     return _stencil7(N, dict(zm=-1.0, ym=-1.0, xm=-1.0, c=6.0, xp=-1.0, yp=-1.0, zp=-1.0))
 
 
+def poisson7_vardiag(N):
+    """7-point 3D Poisson whose diagonal cycles through 6, 6.25, 6.5, 6.75 along
+    the rows (a non-uniform Jacobi vector; still diagonally dominant)."""
+    rp, ci, v = poisson7(N)
+    v = v.copy()
+    rows = np.repeat(np.arange(N ** 3, dtype=np.int64), np.diff(rp))
+    diag = ci == rows
+    v[diag] = 6.0 + 0.25 * (rows[diag] % 4)
+    return rp, ci, v
+
+
 def convdiff7(N, P=(0.5, 0.25, 0.125)):
     """Upwind 7-point convection-diffusion on an N^3 grid, wind along +x,+y,+z."""
     Px, Py, Pz = (float(p) for p in P)

@@ -259,3 +259,21 @@ def test_etype27_small_every_scalar(orc, variant, vname):
     compare(ro, xg, ig)
     k = ro["iters"]
     assert same(H(ig["xr"])[:k], ro["xr"][:k])
+
+
+@pytest.mark.parametrize("variant,vname", VARIANTS + [(2, "pcg")])
+def test_uniform_and_nonuniform_jacobi_paths(orc, variant, vname):
+    """A uniform Jacobi vector (constant diagonal: the preconditioned vectors are
+    formed where they are read) and a non-uniform one (they are stored) both give
+    the oracle's scalars and iterates, bit for bit."""
+    for gen in (inputs.poisson7, inputs.poisson7_vardiag):
+        A = gen(10)
+        M = rpk.Matrix(*A)
+        b = rhs(orc, M, A, inputs.uniform(1000, 77))
+        ro = orc.solve(*A, b, tol=1e-12, maxit=300, variant=variant, record=True, record_xr=True)
+        xg, ig = rpk.solve(M, T(b), tol=1e-12, maxit=300, variant=variant, record=True, record_xr=True)
+        say(gen.__name__, vname, ig["status"], ig["iters"])
+        compare(ro, xg, ig)
+        k = ro["iters"]
+        assert same(H(ig["xr"])[:k], ro["xr"][:k])
+        M.close()
