@@ -201,30 +201,30 @@ __global__ void __launch_bounds__(1024) kb_pipe_init1(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pipe_init2(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   tile_loop<N, 1, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_init2_body<N>(D.A, D.V, D.red, R, rec, s);
+    pipe_init2_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N, bool Mid>
+template <int N, bool Mid, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pipe_P1(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
   tile_loop_publish<N, 4>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P1_body<N, true, Mid>(D.A, D.V, D.red, R, rec, s);
+    pipe_P1_body<N, true, Mid, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N, bool Mid>
+template <int N, bool Mid, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
   tile_loop_publish<N, 3>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pipe_P3_body<N, true, Mid>(D.A, D.V, D.red, R, rec, s);
+    pipe_P3_body<N, true, Mid, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(1024) kb_pipe_P3(Batch B) {
 // the K dots P1 / P3 published for that system and takes its scalar step; the
 // SpMV of every tile of a system that ran goes ahead regardless (it needs
 // neither result, and spmv_go, written by the kernel before, does not change).
-template <int N, int W, int K, int F>
+template <int N, int W, int K, int F, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pipe_spmv_fin(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, K, true);
@@ -247,8 +247,8 @@ __global__ void __launch_bounds__(1024) kb_pipe_spmv_fin(Batch B) {
       block_finalize_last<N, K>(s, D.red, 0);
       if (threadIdx.x == 0) finish_step<N, K, F>(s, D.V);
     }
-    if (W == 0) spmv_body<N>(D.A, D.V.wh, D.V.t, Range{T.lo, T.hi}, s);
-    else spmv_body<N>(D.A, D.V.zh, D.V.v, Range{T.lo, T.hi}, s);
+    if (W == 0) spmv_hat_body<N, Unif>(D.A, D.V.w, D.V.wh, D.V.t, Range{T.lo, T.hi}, s);
+    else spmv_hat_body<N, Unif>(D.A, D.V.z, D.V.zh, D.V.v, Range{T.lo, T.hi}, s);
     __syncthreads();
   }
 }
@@ -293,12 +293,13 @@ __global__ void __launch_bounds__(1024) kb_pcg_S10(Batch B) {
 
 // Third set-up step of the pipelined loop over all tiles: t = A w^ (the loop's
 // own SpMVs are kb_pipe_spmv_fin).
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pipe_spmv(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, true);
-  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { spmv_body<N>(D.A, D.V.wh, D.V.t, R, s); });
+  tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int) {
+    spmv_hat_body<N, Unif>(D.A, D.V.w, D.V.wh, D.V.t, R, s);
+  });
 }
 
 }  // namespace rpk

@@ -86,6 +86,11 @@ inline int keep_slices(const rpk_matrix* A, int nvec) {
 // Jacobi vector; with a uniform Jacobi vector p^ and q^ are never stored and
 // dinv is a scalar, which leaves seven.
 inline int std_vectors(bool unif) { return unif ? 7 : nvec_of(RPK_STD) + 2; }
+// Vectors the pipelined loop keeps cached when they fit: p^, q, q^, y, r, r^, w,
+// t, v and z^, w^ (its other six, s, s^, z, x, r0 and dinv, are always
+// streamed); with a uniform Jacobi vector z^ and w^ are never stored and z
+// (gathered by P2) is kept instead: ten.
+inline int pipe_kept(bool unif) { return unif ? 10 : 11; }
 
 // Whether a solve streams vectors past the Infinity Cache beyond what it always
 // does (Vecs::far): the standard loop when the vectors it touches do not fit in
@@ -93,7 +98,7 @@ inline int std_vectors(bool unif) { return unif ? 7 : nvec_of(RPK_STD) + 2; }
 // keeps do not.  A batch of systems decides the same way on its total number of
 // rows (unif: every system's Jacobi vector is uniform).
 inline bool rows_stream_far(int64_t rows, int variant, bool unif) {
-  const int kept = variant == RPK_STD ? std_vectors(unif) : variant == RPK_PIPELINED ? 11 : 0;
+  const int kept = variant == RPK_STD ? std_vectors(unif) : variant == RPK_PIPELINED ? pipe_kept(unif) : 0;
   return kept > 0 && (double)kept * (double)rows * 8.0 > 0.9 * kInfinityCacheBytes;
 }
 inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_far(A->n, variant, A->unif != 0); }
@@ -102,7 +107,7 @@ inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_f
 // less those streamed past it: x, p, r0 and dinv in the standard loop, x and r0
 // with a uniform Jacobi vector)
 inline int cached_vectors(int variant, bool far, bool unif) {
-  if (variant == RPK_PIPELINED) return far ? 4 : 11;
+  if (variant == RPK_PIPELINED) return far ? 4 : pipe_kept(unif);
   if (variant == RPK_STD) return std_vectors(unif) - (far ? (unif ? 2 : 4) : 0);
   return nvec_of(variant) + 2;
 }

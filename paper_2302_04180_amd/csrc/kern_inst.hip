@@ -27,8 +27,12 @@ rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V
   if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
   if (variant == RPK_PCG) return launch(k_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-  RET_IF(launch(k_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
-  return launch(k_pipe_spmv<N>, G, B, shm_bytes(N, 0, true, B), s, A, V);
+  if (A.unif) {
+    RET_IF(launch(k_pipe_init2<N, true>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+    return launch(k_pipe_spmv<N, true>, G, B, shm_bytes(N, 0, true, B), s, A, V);
+  }
+  RET_IF(launch(k_pipe_init2<N, false>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
+  return launch(k_pipe_spmv<N, false>, G, B, shm_bytes(N, 0, true, B), s, A, V);
 }
 
 template <int N>
@@ -78,15 +82,29 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
   // the SpMVs carry one more workgroup (the finisher of the reduction before them)
   // when the grid has a single one
   const int Gs = G < 2 ? 2 : G;
+  const size_t s4 = shm_bytes(N, 4, false, B), s4t = shm_bytes(N, 4, true, B);
+  const size_t s3 = shm_bytes(N, 3, false, B), s3t = shm_bytes(N, 3, true, B);
+  if (A.unif) {
+    switch (ph) {
+      case 0:
+        return V.far ? launch(k_pipe_P1<N, true, true>, G, B, s4, s, A, V, red)
+                     : launch(k_pipe_P1<N, false, true>, G, B, s4, s, A, V, red);
+      case 1: return launch(k_pipe_spmv_fin<N, 1, 4, FIN_POMEGA, true>, Gs, B, s4t, s, A, V, red);
+      case 2:
+        return V.far ? launch(k_pipe_P3<N, true, true>, G, B, s3, s, A, V, red)
+                     : launch(k_pipe_P3<N, false, true>, G, B, s3, s, A, V, red);
+      default: return launch(k_pipe_spmv_fin<N, 0, 3, FIN_S19, true>, Gs, B, s3t, s, A, V, red);
+    }
+  }
   switch (ph) {
     case 0:
-      return V.far ? launch(k_pipe_P1<N, true>, G, B, shm_bytes(N, 4, false, B), s, A, V, red)
-                   : launch(k_pipe_P1<N, false>, G, B, shm_bytes(N, 4, false, B), s, A, V, red);
-    case 1: return launch(k_pipe_spmv_fin<N, 1, 4, FIN_POMEGA>, Gs, B, shm_bytes(N, 4, true, B), s, A, V, red);
+      return V.far ? launch(k_pipe_P1<N, true, false>, G, B, s4, s, A, V, red)
+                   : launch(k_pipe_P1<N, false, false>, G, B, s4, s, A, V, red);
+    case 1: return launch(k_pipe_spmv_fin<N, 1, 4, FIN_POMEGA, false>, Gs, B, s4t, s, A, V, red);
     case 2:
-      return V.far ? launch(k_pipe_P3<N, true>, G, B, shm_bytes(N, 3, false, B), s, A, V, red)
-                   : launch(k_pipe_P3<N, false>, G, B, shm_bytes(N, 3, false, B), s, A, V, red);
-    default: return launch(k_pipe_spmv_fin<N, 0, 3, FIN_S19>, Gs, B, shm_bytes(N, 3, true, B), s, A, V, red);
+      return V.far ? launch(k_pipe_P3<N, true, false>, G, B, s3, s, A, V, red)
+                   : launch(k_pipe_P3<N, false, false>, G, B, s3, s, A, V, red);
+    default: return launch(k_pipe_spmv_fin<N, 0, 3, FIN_S19, false>, Gs, B, s3t, s, A, V, red);
   }
 }
 
@@ -103,8 +121,12 @@ rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batc
   if (variant == RPK_STD) return launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b);
   if (variant == RPK_PCG) return launch(kb_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, b);
   RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-  RET_IF(launch(kb_pipe_init2<N>, G, B, shm_bytes(N, 1, true, B), s, b));
-  return launch(kb_pipe_spmv<N>, G, B, shm_bytes(N, 0, true, B), s, b);
+  if (b.unif) {
+    RET_IF(launch(kb_pipe_init2<N, true>, G, B, shm_bytes(N, 1, true, B), s, b));
+    return launch(kb_pipe_spmv<N, true>, G, B, shm_bytes(N, 0, true, B), s, b);
+  }
+  RET_IF(launch(kb_pipe_init2<N, false>, G, B, shm_bytes(N, 1, true, B), s, b));
+  return launch(kb_pipe_spmv<N, false>, G, B, shm_bytes(N, 0, true, B), s, b);
 }
 
 template <int N>
@@ -148,15 +170,29 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
       default: return launch(kb_pcg_S10<N>, G, B, 0, s, b);
     }
   }
+  const size_t s4 = shm_bytes(N, 4, false, B), s4t = shm_bytes(N, 4, true, B);
+  const size_t s3 = shm_bytes(N, 3, false, B), s3t = shm_bytes(N, 3, true, B);
+  if (b.unif) {
+    switch (ph) {
+      case 0:
+        return b.far ? launch(kb_pipe_P1<N, true, true>, G, B, s4, s, b)
+                     : launch(kb_pipe_P1<N, false, true>, G, B, s4, s, b);
+      case 1: return launch(kb_pipe_spmv_fin<N, 1, 4, FIN_POMEGA, true>, G, B, s4t, s, b);
+      case 2:
+        return b.far ? launch(kb_pipe_P3<N, true, true>, G, B, s3, s, b)
+                     : launch(kb_pipe_P3<N, false, true>, G, B, s3, s, b);
+      default: return launch(kb_pipe_spmv_fin<N, 0, 3, FIN_S19, true>, G, B, s3t, s, b);
+    }
+  }
   switch (ph) {
     case 0:
-      return b.far ? launch(kb_pipe_P1<N, true>, G, B, shm_bytes(N, 4, false, B), s, b)
-                   : launch(kb_pipe_P1<N, false>, G, B, shm_bytes(N, 4, false, B), s, b);
-    case 1: return launch(kb_pipe_spmv_fin<N, 1, 4, FIN_POMEGA>, G, B, shm_bytes(N, 4, true, B), s, b);
+      return b.far ? launch(kb_pipe_P1<N, true, false>, G, B, s4, s, b)
+                   : launch(kb_pipe_P1<N, false, false>, G, B, s4, s, b);
+    case 1: return launch(kb_pipe_spmv_fin<N, 1, 4, FIN_POMEGA, false>, G, B, s4t, s, b);
     case 2:
-      return b.far ? launch(kb_pipe_P3<N, true>, G, B, shm_bytes(N, 3, false, B), s, b)
-                   : launch(kb_pipe_P3<N, false>, G, B, shm_bytes(N, 3, false, B), s, b);
-    default: return launch(kb_pipe_spmv_fin<N, 0, 3, FIN_S19>, G, B, shm_bytes(N, 3, true, B), s, b);
+      return b.far ? launch(kb_pipe_P3<N, true, false>, G, B, s3, s, b)
+                   : launch(kb_pipe_P3<N, false, false>, G, B, s3, s, b);
+    default: return launch(kb_pipe_spmv_fin<N, 0, 3, FIN_S19, false>, G, B, s3t, s, b);
   }
 }
 

@@ -96,7 +96,10 @@ struct Req {
 };
 
 // A view of the header: which tiles / systems one launch sequence covers.
-enum : int { V_NEW = 0, V_RUN = 1, V_FIN = 2, NVIEW = 3 };
+// A request runs the Unif instantiations (Csr::unif) exactly when its matrix's
+// Jacobi vector is uniform, from its set-up to its last iteration, so each round
+// launches the uniform requests and the others as two views.
+enum : int { V_NEW_U = 0, V_NEW_N = 1, V_RUN_U = 2, V_RUN_N = 3, V_FIN = 4, NVIEW = 5 };
 
 }  // namespace
 
@@ -165,18 +168,13 @@ Batch view(const rpk_server* S, int v) {
   return B;
 }
 
-// Fill view v of the host header image with the systems in `slots_v`; returns
-// the number of tiles (a multiple of 8) through *ntiles.
-rpk_status set_view(rpk_server* S, int v, const std::vector<int>& slots_v, int* ntiles) {
+// Fill view v of the host header image with the systems in `slots_v` (launched
+// with the Unif / Far instantiations when unif / far); returns the number of
+// tiles (a multiple of 8) through *ntiles.
+rpk_status set_view(rpk_server* S, int v, const std::vector<int>& slots_v, bool unif, bool far, int* ntiles) {
   std::vector<int64_t> n;
-  int64_t rows = 0;
-  bool unif = true;
-  for (int k : slots_v) {
-    n.push_back(S->slots[k]->n);
-    rows += S->slots[k]->n;
-    unif = unif && S->slots[k]->A->unif != 0;
-  }
-  S->view_far[v] = rows_stream_far(rows, S->o.solve.variant, unif) ? 1 : 0;
+  for (int k : slots_v) n.push_back(S->slots[k]->n);
+  S->view_far[v] = far ? 1 : 0;
   S->view_unif[v] = unif ? 1 : 0;
   Plan p;
   if (!slots_v.empty()) p = make_plan(n, S->tile, &slots_v);
@@ -234,26 +232,42 @@ struct SStartF {
 rpk_status round(rpk_server* S, const std::vector<int>& fresh, const std::vector<int>& running,
                  std::vector<int>* stopped) {
   const int variant = S->o.solve.variant;
-  int nt_new = 0, nt_run = 0;
   for (int k : fresh) {
     Req* r = S->slots[k];
     const int G = (int)std::max<int64_t>(1, (r->n + S->tile - 1) / S->tile);
     ((SysDesc*)(S->h_hdr.data() + S->off_descs))[k] =
         make_desc(r->A, r->b, r->x, S->budget + r->off, r->gcap, G, variant, S->d_states + k, nullptr);
   }
-  RET_IF(set_view(S, V_NEW, fresh, &nt_new));
-  RET_IF(set_view(S, V_RUN, running, &nt_run));
-  if (S->view_far[V_RUN])
+  // [0]: requests whose Jacobi vector is uniform, [1]: the others
+  std::vector<int> fresh_v[2], run_v[2];
+  int64_t rows = 0;
+  for (int k : fresh) fresh_v[S->slots[k]->A->unif ? 0 : 1].push_back(k);
+  for (int k : running) {
+    run_v[S->slots[k]->A->unif ? 0 : 1].push_back(k);
+    rows += S->slots[k]->n;
+  }
+  // the two views share the Infinity Cache: one decision on all rows in flight
+  const bool far = rows_stream_far(rows, variant, run_v[1].empty());
+  int nt_new[2] = {0, 0}, nt_run[2] = {0, 0};
+  for (int u = 0; u < 2; ++u) {
+    RET_IF(set_view(S, V_NEW_U + u, fresh_v[u], u == 0, far, &nt_new[u]));
+    RET_IF(set_view(S, V_RUN_U + u, run_v[u], u == 0, far, &nt_run[u]));
+  }
+  if (far)
     for (int k : running) S->slots[k]->streamed = true;
   RET_IF(upload(S));
-  if (!fresh.empty())
-    RET_IF(by_fpe<SStartF>(S->N, variant, g_of(nt_new), gf_of(fresh.size()), S->block, S->stream, view(S, V_NEW),
-                           S->o.solve.tol, S->o.solve.maxit));
+  for (int u = 0; u < 2; ++u)
+    if (!fresh_v[u].empty())
+      RET_IF(by_fpe<SStartF>(S->N, variant, g_of(nt_new[u]), gf_of(fresh_v[u].size()), S->block, S->stream,
+                             view(S, V_NEW_U + u), S->o.solve.tol, S->o.solve.maxit));
   const int chunk = S->o.chunk > 0 ? S->o.chunk : 4;
-  const Batch run = view(S, V_RUN);
-  const int Gf = gf_of(running.size());
+  const Batch run[2] = {view(S, V_RUN_U), view(S, V_RUN_N)};
   for (int it = 0; it < chunk; ++it)
-    for (int ph = 0; ph < S->nph; ++ph) RET_IF(by_fpe<SPhaseF>(S->N, variant, ph, g_of(nt_run), Gf, S->block, S->stream, run));
+    for (int ph = 0; ph < S->nph; ++ph)
+      for (int u = 0; u < 2; ++u)
+        if (!run_v[u].empty())
+          RET_IF(by_fpe<SPhaseF>(S->N, variant, ph, g_of(nt_run[u]), gf_of(run_v[u].size()), S->block, S->stream,
+                                 run[u]));
   S->st.iterations += chunk;
   HIPCHK(hipMemcpyAsync(S->h_states, S->d_states, (size_t)S->o.max_slots * sizeof(State),
                         hipMemcpyDeviceToHost, S->stream));
@@ -264,7 +278,7 @@ rpk_status round(rpk_server* S, const std::vector<int>& fresh, const std::vector
   if (stopped->empty()) return RPK_OK;
   // exact true residual of the stopped systems
   int nt_fin = 0;
-  RET_IF(set_view(S, V_FIN, *stopped, &nt_fin));
+  RET_IF(set_view(S, V_FIN, *stopped, false, false, &nt_fin));
   RET_IF(upload(S));
   RET_IF(KernB<4>::resid(g_of(nt_fin), gf_of(stopped->size()), S->block, S->stream, view(S, V_FIN)));
   HIPCHK(hipMemcpyAsync(S->h_states, S->d_states, (size_t)S->o.max_slots * sizeof(State),

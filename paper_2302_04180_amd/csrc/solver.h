@@ -26,6 +26,11 @@
 //   P4: S18 SpMV                                    | workgroup 0: S19
 // s and z do not change between S2/S4 and S16, so their two S16 dots are taken
 // where they are produced (P1 reads r0 once instead of P3 reading s and z).
+// z^ (S9) and w^ (S17) are the loop's only preconditioned vectors formed as
+// RN(dinv_i v_i) (p^, s^, q^, r^ follow their own recurrences): with a uniform
+// Jacobi vector (the Unif instantiations) they are formed where they are read --
+// at the gathers of P2 / P4 and in S3 / S14 -- and never stored: 35 vector
+// streams per iteration instead of 41.
 // Every update is the explicit fma written next to it; scalar steps are single
 // IEEE operations in one thread, in the order of the figures.
 #pragma once
@@ -586,8 +591,9 @@ __device__ __forceinline__ void pipe_init1_body(const Csr& A, const Vecs& V, con
   publish_step<N, 1, FIN_PENTRY1>(d, s, V, red, rec);
 }
 
-// set-up 2: w = A r^, w^ = M^-1 w ; partial <r0, w> (slot 1)
-template <int N>
+// set-up 2: w = A r^, w^ = M^-1 w (formed where read for a uniform Jacobi
+// vector) ; partial <r0, w> (slot 1)
+template <int N, bool Unif>
 __device__ __forceinline__ void pipe_init2_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                                 const Shm<N>& s) {
   Dot<N> d[1];
@@ -598,7 +604,7 @@ __device__ __forceinline__ void pipe_init2_body(const Csr& A, const Vecs& V, con
     const double wi = rows_wave<N>(A, V.rh, i, ok, s.wsa);
     if (ok) {
       V.w[i] = wi;
-      V.wh[i] = A.dinv[i] * wi;
+      if constexpr (!Unif) V.wh[i] = A.dinv[i] * wi;
       d[0].add(V.r0[i], wi, s.sa, &s.flag[0]);
     }
   }
@@ -616,21 +622,38 @@ __device__ __forceinline__ void spmv_body(const Csr& A, const double* in, double
   }
 }
 
-// P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3)
-template <int N, bool Defer = false, bool Mid = false>
+// out = A M^-1 v on rows R: gathers the stored M^-1 v (vh), or v scaled by du
+template <int N, bool Unif>
+__device__ __forceinline__ void spmv_hat_body(const Csr& A, const double* v, const double* vh, double* out, Range R,
+                                              const Shm<N>& s) {
+  for (int base = R.lo; base < R.hi; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool ok = i < R.hi;
+    const double y = rows_wave_hat<N, Unif>(A, v, vh, i, ok, s.wsa);
+    if (ok) out[i] = y;
+  }
+}
+
+// P1: S1..S7, S9, the partials of S8 (slots 0, 1) and of <r0,s>, <r0,z> (slots 2, 3).
+// Unif: w^ = RN(du w) and the old z^ = RN(du z) are formed here (S3), z^ is not
+// stored (P2 gathers z), and z and w stay cached for P2 / P3.
+template <int N, bool Defer, bool Mid, bool Unif>
 __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
-  const double alpha = st->alpha, beta = st->beta, omega = st->omega;
+  const double alpha = st->alpha, beta = st->beta, omega = st->omega, du = A.du;
   Dot<N> d[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) d[j].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double rh = ld_v<Mid>(&V.rh[i]), w = ld_v<Mid>(&V.w[i]), wh = V.wh[i], r0 = ld_far(&V.r0[i]);
-    const double sh_old = ld_far(&V.sh[i]), z_old = ld_far(&V.z[i]);
+    const double rh = ld_v<Mid>(&V.rh[i]), r0 = ld_far(&V.r0[i]);
+    const double w = Unif ? V.w[i] : ld_v<Mid>(&V.w[i]);
+    const double wh = Unif ? du * w : V.wh[i];
+    const double sh_old = ld_far(&V.sh[i]), z_old = Unif ? V.z[i] : ld_far(&V.z[i]);
+    const double zh_old = Unif ? du * z_old : V.zh[i];
     const double ph = fma(beta, fma(-omega, sh_old, ld_v<Mid>(&V.ph[i])), rh);  // S1
     const double sv = fma(beta, fma(-omega, z_old, ld_far(&V.s[i])), w);  // S2
-    const double sh = fma(beta, fma(-omega, V.zh[i], sh_old), wh);      // S3
+    const double sh = fma(beta, fma(-omega, zh_old, sh_old), wh);       // S3
     const double z = fma(beta, fma(-omega, V.v[i], z_old), V.t[i]);     // S4
     const double q = fma(-alpha, sv, ld_v<Mid>(&V.r[i]));               // S5
     const double qh = fma(-alpha, sh, rh);                              // S6
@@ -638,11 +661,12 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
     st_v<Mid>(&V.ph[i], ph);
     st_far(&V.s[i], sv);
     st_far(&V.sh[i], sh);
-    st_far(&V.z[i], z);
+    if constexpr (Unif) V.z[i] = z;
+    else st_far(&V.z[i], z);
     st_v<Mid>(&V.q[i], q);
     st_v<Mid>(&V.qh[i], qh);
     st_v<Mid>(&V.y[i], y);
-    V.zh[i] = ld_far(&A.dinv[i]) * z;                                   // S9
+    if constexpr (!Unif) V.zh[i] = ld_far(&A.dinv[i]) * z;              // S9
     d[0].add(q, y, s.sa, &s.flag[0]);                                 // S8
     d[1].add(y, y, s.sa + SA_D, &s.flag[1]);
     d[2].add(r0, sv, s.sa + 2 * SA_D, &s.flag[2]);                    // S16: <r0,s>
@@ -651,12 +675,14 @@ __device__ __forceinline__ void pipe_P1_body(const Csr& A, const Vecs& V, const 
   publish_or_defer<N, 4, FIN_POMEGA, Defer>(d, s, V, red, rec);
 }
 
-// P3: S12..S15, S17 and the partials of <r0,r>, <r0,w> (S16) and <r,r> (slots 0..2)
-template <int N, bool Defer = false, bool Mid = false>
+// P3: S12..S15, S17 and the partials of <r0,r>, <r0,w> (S16) and <r,r> (slots 0..2).
+// Unif: z^ = RN(du z) and the old w^ = RN(du w) are formed here (S14), w^ is not
+// stored (P4 gathers w), and w stays cached for P4.
+template <int N, bool Defer, bool Mid, bool Unif>
 __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                              const Shm<N>& s) {
   const State* st = V.st;
-  const double alpha = st->alpha, omega = st->omega;
+  const double alpha = st->alpha, omega = st->omega, du = A.du;
   const int iter = st->iter;
   Dot<N> d[3];
 #pragma unroll
@@ -665,13 +691,18 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
     const double qh = ld_v<Mid>(&V.qh[i]), y = ld_v<Mid>(&V.y[i]), r0 = ld_far(&V.r0[i]);
     const double x = fma(omega, qh, fma(alpha, ld_v<Mid>(&V.ph[i]), ld_far(&V.x[i])));  // S12
     const double r = fma(-omega, y, ld_v<Mid>(&V.q[i]));                               // S13
-    const double rh = fma(-omega, fma(-alpha, V.zh[i], V.wh[i]), qh);      // S14
+    const double zh = Unif ? du * V.z[i] : V.zh[i], wh_old = Unif ? du * V.w[i] : V.wh[i];
+    const double rh = fma(-omega, fma(-alpha, zh, wh_old), qh);            // S14
     const double w = fma(-omega, fma(-alpha, V.v[i], V.t[i]), y);          // S15
     st_far(&V.x[i], x);
     st_v<Mid>(&V.r[i], r);
     st_v<Mid>(&V.rh[i], rh);
-    st_v<Mid>(&V.w[i], w);
-    V.wh[i] = ld_far(&A.dinv[i]) * w;                                      // S17
+    if constexpr (Unif) {
+      V.w[i] = w;
+    } else {
+      st_v<Mid>(&V.w[i], w);
+      V.wh[i] = ld_far(&A.dinv[i]) * w;                                    // S17
+    }
     record_xr(V, iter, A.n, i, x, r);
     d[0].add(r0, r, s.sa, &s.flag[0]);                                 // S16
     d[1].add(r0, w, s.sa + SA_D, &s.flag[1]);
@@ -827,28 +858,28 @@ __global__ void __launch_bounds__(1024) k_pipe_init1(Csr A, Vecs V, Red red) {
   pipe_init1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pipe_init2(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   shm_init(s, 1);
-  pipe_init2_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_init2_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 // Third set-up step of the pipelined loop: t = A w^ (the loop's own SpMVs are
 // k_pipe_spmv_fin below).  It still runs when the set-up stops at an iteration
 // limit of 0, so that a resumed solve finds t in place.
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pipe_spmv(Csr A, Vecs V) {
   if (V.st->done && V.st->resumable != 1) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, true);
-  spmv_body<N>(A, V.wh, V.t, my_rows(A.n), s);
+  spmv_hat_body<N, Unif>(A, V.w, V.wh, V.t, my_rows(A.n), s);
 }
 
 // P1 and P3 leave their reduction to the SpMV kernel that follows them
 // (k_pipe_spmv_fin), and tell its SpMV workgroups whether they ran.
-template <int N, bool Mid>
+template <int N, bool Mid, bool Unif>
 __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   const int done = V.st->done;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
@@ -856,10 +887,10 @@ __global__ void __launch_bounds__(1024) k_pipe_P1(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 4, false);
   shm_init(s, 4);
-  pipe_P1_body<N, true, Mid>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P1_body<N, true, Mid, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N, bool Mid>
+template <int N, bool Mid, bool Unif>
 __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   const int done = V.st->done;
   if (blockIdx.x == 0 && threadIdx.x == 0) V.st->spmv_go = !done;
@@ -867,7 +898,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 3, false);
   shm_init(s, 3);
-  pipe_P3_body<N, true, Mid>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pipe_P3_body<N, true, Mid, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 // P2 (W = 1: v = A z^, after P1, finishing S11) and P4 (W = 0: t = A w^, after
@@ -877,7 +908,7 @@ __global__ void __launch_bounds__(1024) k_pipe_P3(Csr A, Vecs V, Red red) {
 // kernel before wrote: `done` may change under them here.  So a P4 whose step
 // stops the solve at its iteration limit still computes the whole t (S18 of the
 // next iteration) that a resumed solve needs.
-template <int N, int W, int K, int F>
+template <int N, int W, int K, int F, bool Unif>
 __global__ void __launch_bounds__(1024) k_pipe_spmv_fin(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   if (blockIdx.x == 0) {
@@ -891,8 +922,8 @@ __global__ void __launch_bounds__(1024) k_pipe_spmv_fin(Csr A, Vecs V, Red red) 
   Shm<N> s = shm_carve<N>(smem, 0, true);
   const int G = gridDim.x - 1;
   const Range R = block_rows(A.n, xcd_block(blockIdx.x - 1, G), G);
-  if (W == 0) spmv_body<N>(A, V.wh, V.t, R, s);
-  else spmv_body<N>(A, V.zh, V.v, R, s);
+  if (W == 0) spmv_hat_body<N, Unif>(A, V.w, V.wh, V.t, R, s);
+  else spmv_hat_body<N, Unif>(A, V.z, V.zh, V.v, R, s);
 }
 
 template <int N>
