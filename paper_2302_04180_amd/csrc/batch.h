@@ -256,12 +256,12 @@ __global__ void __launch_bounds__(1024) kb_pipe_spmv_fin(Batch B) {
 // ---------------------------------------------------------------------------
 // preconditioned CG (Fig. 1)
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pcg_init(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   tile_loop<N, 2, false>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pcg_init_body<N>(D.A, D.V, D.red, R, rec, s);
+    pcg_init_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -274,21 +274,21 @@ __global__ void __launch_bounds__(1024) kb_pcg_S1(Batch B) {
   });
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pcg_S3(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pcg_S3_body<N>(D.A, D.V, D.red, R, rec, s);
+    pcg_S3_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) kb_pcg_S10(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { pcg_S10_body(D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { pcg_S10_body<Unif>(D.A, D.V, R); });
 }
 
 // Third set-up step of the pipelined loop over all tiles: t = A w^ (the loop's

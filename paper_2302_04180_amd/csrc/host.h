@@ -109,7 +109,7 @@ inline bool streams_far(const rpk_matrix* A, int variant) { return rows_stream_f
 inline int cached_vectors(int variant, bool far, bool unif) {
   if (variant == RPK_PIPELINED) return far ? 4 : pipe_kept(unif);
   if (variant == RPK_STD) return std_vectors(unif) - (far ? (unif ? 2 : 4) : 0);
-  return nvec_of(variant) + 2;
+  return unif ? nvec_of(variant) : nvec_of(variant) + 2;  // PCG: r, p, d, y, x, dinv (r, p, d, x)
 }
 
 template <template <int> class F, typename... Args>

@@ -25,7 +25,9 @@ rpk_status Kern<N>::spmv(int G, int B, hipStream_t s, Csr A, const double* x, do
 template <int N>
 rpk_status Kern<N>::init(int variant, int G, int B, hipStream_t s, Csr A, Vecs V, Red red) {
   if (variant == RPK_STD) return launch(k_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-  if (variant == RPK_PCG) return launch(k_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
+  if (variant == RPK_PCG)
+    return A.unif ? launch(k_pcg_init<N, true>, G, B, shm_bytes(N, 2, true, B), s, A, V, red)
+                  : launch(k_pcg_init<N, false>, G, B, shm_bytes(N, 2, true, B), s, A, V, red);
   RET_IF(launch(k_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
   if (A.unif) {
     RET_IF(launch(k_pipe_init2<N, true>, G, B, shm_bytes(N, 1, true, B), s, A, V, red));
@@ -75,8 +77,11 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
   if (variant == RPK_PCG) {
     switch (ph) {
       case 0: return launch(k_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 1: return launch(k_pcg_S3<N>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
-      default: return launch(k_pcg_S10<N>, G, B, 0, s, A, V);
+      case 1:
+        return A.unif ? launch(k_pcg_S3<N, true>, G, B, shm_bytes(N, 2, false, B), s, A, V, red)
+                      : launch(k_pcg_S3<N, false>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      default:
+        return A.unif ? launch(k_pcg_S10<N, true>, G, B, 0, s, A, V) : launch(k_pcg_S10<N, false>, G, B, 0, s, A, V);
     }
   }
   // the SpMVs carry one more workgroup (the finisher of the reduction before them)
@@ -119,7 +124,9 @@ template <int N>
 rpk_status KernB<N>::init(int variant, int G, int Gf, int B, hipStream_t s, Batch b) {
   (void)Gf;
   if (variant == RPK_STD) return launch(kb_std_init<N>, G, B, shm_bytes(N, 1, true, B), s, b);
-  if (variant == RPK_PCG) return launch(kb_pcg_init<N>, G, B, shm_bytes(N, 2, true, B), s, b);
+  if (variant == RPK_PCG)
+    return b.unif ? launch(kb_pcg_init<N, true>, G, B, shm_bytes(N, 2, true, B), s, b)
+                  : launch(kb_pcg_init<N, false>, G, B, shm_bytes(N, 2, true, B), s, b);
   RET_IF(launch(kb_pipe_init1<N>, G, B, shm_bytes(N, 1, true, B), s, b));
   if (b.unif) {
     RET_IF(launch(kb_pipe_init2<N, true>, G, B, shm_bytes(N, 1, true, B), s, b));
@@ -153,10 +160,12 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
     }
     switch (ph) {
       case 0:
-        return b.far ? launch(kb_std_A<N, true, false>, G, B, 0, s, b) : launch(kb_std_A<N, false, false>, G, B, 0, s, b);
+        return b.far ? launch(kb_std_A<N, true, false>, G, B, 0, s, b)
+                     : launch(kb_std_A<N, false, false>, G, B, 0, s, b);
       case 1: return launch(kb_std_B<N, false>, G, B, s1, s, b);
       case 2:
-        return b.far ? launch(kb_std_C<N, true, false>, G, B, 0, s, b) : launch(kb_std_C<N, false, false>, G, B, 0, s, b);
+        return b.far ? launch(kb_std_C<N, true, false>, G, B, 0, s, b)
+                     : launch(kb_std_C<N, false, false>, G, B, 0, s, b);
       case 3: return launch(kb_std_D<N, false>, G, B, s2, s, b);
       default:
         return b.far ? launch(kb_std_E<N, true, false>, G, B, s2e, s, b)
@@ -166,8 +175,11 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
   if (variant == RPK_PCG) {
     switch (ph) {
       case 0: return launch(kb_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, b);
-      case 1: return launch(kb_pcg_S3<N>, G, B, shm_bytes(N, 2, false, B), s, b);
-      default: return launch(kb_pcg_S10<N>, G, B, 0, s, b);
+      case 1:
+        return b.unif ? launch(kb_pcg_S3<N, true>, G, B, shm_bytes(N, 2, false, B), s, b)
+                      : launch(kb_pcg_S3<N, false>, G, B, shm_bytes(N, 2, false, B), s, b);
+      default:
+        return b.unif ? launch(kb_pcg_S10<N, true>, G, B, 0, s, b) : launch(kb_pcg_S10<N, false>, G, B, 0, s, b);
     }
   }
   const size_t s4 = shm_bytes(N, 4, false, B), s4t = shm_bytes(N, 4, true, B);

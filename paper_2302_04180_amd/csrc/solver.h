@@ -712,10 +712,12 @@ __device__ __forceinline__ void pipe_P3_body(const Csr& A, const Vecs& V, const 
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioned CG (Fig. 1): vectors r, p, d (in V.s), y; x, b
+// Preconditioned CG (Fig. 1): vectors r, p, d (in V.s), y; x, b.  With a
+// uniform Jacobi vector (Unif) y = RN(du r) is formed where it is read (S5 in
+// S3, and S10) and never stored: 11 vector streams per iteration instead of 13.
 // ---------------------------------------------------------------------------
 // set-up: r = b - A x0, y = M^-1 r, p = y ; partials <y,r>, <r,r>
-template <int N>
+template <int N, bool Unif>
 __device__ __forceinline__ void pcg_init_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                               const Shm<N>& s) {
   Dot<N> d[2];
@@ -727,9 +729,9 @@ __device__ __forceinline__ void pcg_init_body(const Csr& A, const Vecs& V, const
     const double t = rows_wave<N>(A, V.x, i, ok, s.wsa);
     if (ok) {
       const double ri = V.b[i] - t;
-      const double yi = A.dinv[i] * ri;
+      const double yi = (Unif ? A.du : A.dinv[i]) * ri;
       V.r[i] = ri;
-      V.y[i] = yi;
+      if constexpr (!Unif) V.y[i] = yi;
       V.p[i] = yi;
       d[0].add(yi, ri, s.sa, &s.flag[0]);
       d[1].add(ri, ri, s.sa + SA_D, &s.flag[1]);
@@ -758,7 +760,7 @@ __device__ __forceinline__ void pcg_S1_body(const Csr& A, const Vecs& V, const R
 }
 
 // S3 x = fma(rho, p, x), S4 r = fma(-rho, d, r), S5 y = M^-1 r ; partials <y,r>, <r,r> (S7, S8)
-template <int N>
+template <int N, bool Unif>
 __device__ __forceinline__ void pcg_S3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                             const Shm<N>& s) {
   const State* st = V.st;
@@ -770,10 +772,10 @@ __device__ __forceinline__ void pcg_S3_body(const Csr& A, const Vecs& V, const R
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
     const double x = fma(rho, V.p[i], V.x[i]);    // S3
     const double r = fma(-rho, V.s[i], V.r[i]);   // S4
-    const double y = A.dinv[i] * r;               // S5
+    const double y = (Unif ? A.du : A.dinv[i]) * r;  // S5
     V.x[i] = x;
     V.r[i] = r;
-    V.y[i] = y;
+    if constexpr (!Unif) V.y[i] = y;
     record_xr(V, iter, A.n, i, x, r);
     d[0].add(y, r, s.sa, &s.flag[0]);             // S7
     d[1].add(r, r, s.sa + SA_D, &s.flag[1]);      // S8
@@ -782,9 +784,11 @@ __device__ __forceinline__ void pcg_S3_body(const Csr& A, const Vecs& V, const R
 }
 
 // S10 p = fma(alpha, p, y)
-__device__ __forceinline__ void pcg_S10_body(const Vecs& V, Range R) {
-  const double alpha = V.st->alpha;
-  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) V.p[i] = fma(alpha, V.p[i], V.y[i]);
+template <bool Unif>
+__device__ __forceinline__ void pcg_S10_body(const Csr& A, const Vecs& V, Range R) {
+  const double alpha = V.st->alpha, du = A.du;
+  for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x)
+    V.p[i] = fma(alpha, V.p[i], Unif ? du * V.r[i] : V.y[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -926,12 +930,12 @@ __global__ void __launch_bounds__(1024) k_pipe_spmv_fin(Csr A, Vecs V, Red red) 
   else spmv_hat_body<N, Unif>(A, V.z, V.zh, V.v, R, s);
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pcg_init(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   shm_init(s, 2);
-  pcg_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pcg_init_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N>
@@ -943,22 +947,22 @@ __global__ void __launch_bounds__(1024) k_pcg_S1(Csr A, Vecs V, Red red) {
   pcg_S1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pcg_S3(Csr A, Vecs V, Red red) {
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   shm_init(s, 2);
-  pcg_S3_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pcg_S3_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 // S10 opens the next iteration: after a stop at the iteration limit it is left
 // to the resumed solve (it is not idempotent, and the kernels of the iterations
 // still queued behind the stop see the same state).
-template <int N>
+template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pcg_S10(Csr A, Vecs V) {
   if (V.st->done) return;
-  pcg_S10_body(V, my_rows(A.n));
+  pcg_S10_body<Unif>(A, V, my_rows(A.n));
 }
 
 }  // namespace rpk
