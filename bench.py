@@ -332,6 +332,11 @@ def batched_leg(torch, rpk, inputs, reps=3):
     t_alone = time.perf_counter() - t1
     ok = all(i["status"] == "OK" for i in infos)
     alg_bytes = sum(i["iters"] * std_bytes(M) for i, M in zip(infos, Ms))
+    # where the batch loses bandwidth: the share of its rows still iterating at
+    # each tenth of the longest solve (systems that converged leave the launches)
+    imax = max(iters)
+    active = [round(sum(M.n for M, it in zip(Ms, iters) if it > (d * imax) // 10) / rows, 3) for d in range(10)]
+    busy = sum(it * M.n for M, it in zip(Ms, iters)) / (imax * rows)
     for M in Ms:
         M.close()
     return {"systems": len(infos), "rows": rows, "nnz": nnz, "all_converged": ok,
@@ -340,7 +345,9 @@ def batched_leg(torch, rpk, inputs, reps=3):
             "alone_solves_per_s": round(len(infos) / t_alone, 1),
             "algorithmic_GBps": round(alg_bytes / dt / 1e9, 1),
             "roofline_frac": round(alg_bytes / dt / 1e9 / HBM_PEAK_GBS, 4),
-            "sampled_results_equal_alone": same, "launch": infos[0]["used"]}
+            "sampled_results_equal_alone": same, "launch": infos[0]["used"],
+            "active_rows_share_by_tenth_of_longest_solve": active,
+            "row_iterations_over_longest_times_rows": round(busy, 3)}
 
 
 def etype_leg(torch, rpk, inputs, reps=2):
@@ -404,8 +411,9 @@ def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.
     round(n^(1/3)) clamped to [16, 128]), Poisson or convection-diffusion (Peclet
     U[0.1, 2]) from a seeded pool of matrices, right-hand side U(-1, 1) seeded by
     the request id.  Arrival rates: each of `loads` x the closed-loop saturation
-    rate, one after the other on the same server (the first is reported at the
-    top level, the others under "at_<load>").  Afterwards the first measured
+    rate (steady state with 64 requests outstanding), one after the other on the
+    same server (the first is reported at the top level, the others under
+    "at_<load>").  Afterwards the first measured
     request to finish in each of `bins` log-spaced bins of n is solved again
     alone and compared with its served result bit for bit."""
     import numpy as np
@@ -421,8 +429,9 @@ def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.
             A = inputs.convdiff7(edge, (pe, pe / 2, pe / 4))
         pool.append(rpk.Matrix(*A))
     # request i draws pool matrix pick[i] and a right-hand side seeded by i: ids
-    # 0..63 measure saturation, then each load takes the next warm + n_req ids
-    pick = rng.integers(0, pool_size, size=64 + len(loads) * (warm + n_req))
+    # 0..n_sat-1 measure saturation, then each load takes the next warm + n_req ids
+    n_sat, depth = 320, 64
+    pick = rng.integers(0, pool_size, size=n_sat + len(loads) * (warm + n_req))
     srv = rpk.Server(hbm_budget=2 << 30, max_slots=64, chunk=4, tol=1e-9, maxit=10000, variant=rpk.PIPELINED)
 
     def request(r):
@@ -432,13 +441,23 @@ def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.
         b = torch.rand(M.n, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
         return M, b, torch.zeros(M.n, dtype=torch.float64, device="cuda")
 
-    # closed-loop saturation: 64 requests at once
-    reqs = [request(k) for k in range(64)]
+    # closed-loop saturation: `depth` requests outstanding, each completion
+    # replaced by the next request; the rate over the completions between the
+    # first and the last quarter of the run (steady state, no ramp or drain)
+    out, done_at, nxt = {}, [], 0
     t0 = time.perf_counter()
-    ts = [srv.submit(M, b, x) for M, b, x in reqs]
-    for t in ts:
-        srv.wait(t)
-    mu = 64 / (time.perf_counter() - t0)
+    while nxt < n_sat or out:
+        while nxt < n_sat and len(out) < depth:
+            M, b, x = request(nxt)
+            out[srv.submit(M, b, x)] = (M, b, x)
+            nxt += 1
+        for t in list(out):
+            if srv.poll(t) is not None:
+                out.pop(t)
+                done_at.append(time.perf_counter() - t0)
+        time.sleep(0.0002)
+    q1, q3 = n_sat // 4, 3 * n_sat // 4
+    mu = (q3 - q1) / (done_at[q3] - done_at[q1])
     lo_n, hi_n = np.log(4096), np.log(2.1e6)
     samples = {}  # size bin -> (M, b, x as served, result)
 
@@ -480,7 +499,7 @@ def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.
                 "queue_ms_p50": round(float(np.percentile(qms, 50)), 2),
                 "queue_ms_p99": round(float(np.percentile(qms, 99)), 2)}
 
-    phases = [open_loop(ld, 64 + k * (warm + n_req)) for k, ld in enumerate(loads)]
+    phases = [open_loop(ld, n_sat + k * (warm + n_req)) for k, ld in enumerate(loads)]
     st = srv.stats()
     srv.close()
     equal, sizes = 0, []
@@ -492,7 +511,8 @@ def serving_leg(torch, rpk, inputs, n_req=1000, warm=50, pool_size=48, loads=(0.
     for M in pool:
         M.close()
     res = {"requests": n_req, "warmup_requests": warm, "saturation_solves_per_s": round(mu, 1),
-           "load": loads[0]}
+           "saturation_measure": "closed loop, %d requests outstanding, %d requests, rate over the middle half"
+                                 % (depth, n_sat), "load": loads[0]}
     res.update(phases[0])
     for ld, ph in zip(loads[1:], phases[1:]):
         res["at_%g" % ld] = ph
