@@ -36,12 +36,13 @@ MAXIT = 5000
 # Infinity Cache), from two rocprofv3 --pmc passes over
 # `python3 bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; median per launch),
 # each scaled by what the same counter reads for the plain copy kernel of that
-# workload (512 MiB read + 512 MiB written).  Valid only while the kernel
-# sources still have the digest they had when the counters were taken and the
-# solve runs the same FPE length.
-TRAFFIC = {"phase": 3, "kernel": "k_std_D<3>", "fpe": 3, "bytes": 229595064,
-           "fetch_scale": 1.9999, "write_scale": 1.0000,
-           "src_sha256": "bf564ae03c680c0821a765decb1bfdc1fd1c3555de1c9ae442d0f6c8d7fb667e"}
+# workload (512 MiB read + 512 MiB written), and the kernel's average duration in
+# the rocprofv3 kernel trace of the bench (launches of the 128^3 section longer
+# than 8 us).  Valid only while the kernel sources still have the digest they
+# had when the profiles were taken and the solve runs the same FPE length.
+TRAFFIC = {"phase": 3, "kernel": "k_std_D<3, true>", "fpe": 3, "bytes": 213169679,
+           "fetch_scale": 1.9999, "write_scale": 1.0000, "trace_busy_avg_us": 54.2,
+           "src_sha256": "2ee5edc6c7bc84c5c61acc478a0a06ca2e8609f9a0931aca7edef1b437fd5d70"}
 
 
 KERNEL_SOURCES = ("device.h", "kernels.h", "solver.h")
@@ -615,16 +616,21 @@ def main():
     by = algorithmic_bytes(n, nnz)
     dom = max(range(5), key=lambda k: tinfo["phase_ms"][k])
     avg_s = tinfo["phase_ms"][dom] / tinfo["phase_launches"][dom] / 1e3
-    dom_bytes = by["std_kernel_unif"][dom]  # the 7-point Poisson has a uniform Jacobi vector
+    dom_bytes = by["std_kernel"][dom]
     achieved = dom_bytes / avg_s / 1e9
-    traffic = None
+    traffic, trace_us = None, None
     if (TRAFFIC and TRAFFIC["src_sha256"] == kernel_digest() and TRAFFIC["phase"] == dom
             and TRAFFIC["fpe"] == tinfo["used"]["fpe"]):
-        traffic = TRAFFIC["bytes"]
+        traffic, trace_us = TRAFFIC["bytes"], TRAFFIC["trace_busy_avg_us"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[dom], "bytes_per_launch": dom_bytes,
-                "reference_bytes_per_launch": by["std_kernel"][dom], "avg_launch_us": round(avg_s * 1e6, 2)}
+                # what the kernel moves with the uniform Jacobi vector of the 7-point Poisson
+                "moved_bytes_per_launch": by["std_kernel_unif"][dom], "avg_launch_us": round(avg_s * 1e6, 2),
+                # HIP events around direct launches include the dispatch of each kernel (a few us);
+                # the kernel trace of the same sources times the kernels alone
+                "trace_avg_us": trace_us,
+                "trace_frac": round(dom_bytes / (trace_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if trace_us else None}
 
     result = {
         "metric": METRIC, "value": round(exact_ips, 2), "unit": "iters/s", "n_gpus": 1,
