@@ -414,15 +414,6 @@ __device__ inline void sa_normalize_wave(long long* acc, int& lo, int& hi) {
   __builtin_amdgcn_wave_barrier();
 }
 
-// grid digit holding the leading bit of a non-zero finite double
-__device__ __forceinline__ int top_digit(double x) {
-  bool neg;
-  unsigned long long m;
-  int e;
-  decode(x, neg, m, e);
-  return (e - SA_LSB + (63 - __clzll((long long)m))) >> 5;
-}
-
 // ---------------------------------------------------------------------------
 // Exact accumulation of products into an FPE with long-accumulator fallback
 // ---------------------------------------------------------------------------

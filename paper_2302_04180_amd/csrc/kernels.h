@@ -23,8 +23,9 @@ constexpr int MAX_DOTS = 8;  // reduction slots in the workspace
 // Exact cross-lane reduction: each workgroup sums its lanes' FPE components as
 // integers in a window of WIN digits of the long-accumulator grid, anchored at
 // the workgroup's leading digit, and adds the window into the dot's global long
-// accumulator.  Digits that fall below the window (data spread over more than
-// ~350 bits) go to the long accumulator directly, so nothing is ever dropped.
+// accumulator.  Digits that fall below the window (components more than about
+// 290 bits below the workgroup's largest) go to the long accumulator directly,
+// so nothing is ever dropped.
 constexpr int WIN = 12;
 // Lightweight mode: FPE length 8; each workgroup publishes a record of LW_REC
 // doubles per dot (8 components, the plain tail, the flags as a double).
@@ -91,15 +92,18 @@ struct Red {
 // ---------------------------------------------------------------------------
 // lanes per scatter round: all 64 for workgroups of up to 512 threads, 32 for larger ones
 __host__ __device__ inline int scat_rows(int block) { return block <= 512 ? 64 : 32; }
+// LDS stride of the scatter rows (digits): one digit of padding puts the rows of
+// 16 consecutive lanes on distinct banks
+constexpr int ROW_STRIDE = WIN + 1;
 
 __host__ __device__ inline size_t shm_bytes(int N, int K, bool rows, int block) {
   (void)rows;
   const size_t nw = (size_t)block / 64;
   const size_t sa = (N > 0 && N != LW8) ? (size_t)K * SA_D * 8 : 0;
-  // scatter rows (nw x rows x WIN); the row-fallback accumulators (nw x SA_D)
+  // scatter rows (nw x rows x ROW_STRIDE); the row-fallback accumulators (nw x SA_D)
   // use the same space at other times
-  const size_t scat = (N > 0) ? nw * scat_rows(block) * WIN * 8 : 0;
-  const size_t wsum = (N > 0) ? (size_t)16 * WIN * (K > 0 ? K : 1) * 8 : 0;
+  const size_t scat = (N > 0) ? nw * scat_rows(block) * ROW_STRIDE * 8 : 0;
+  const size_t wsum = (N > 0) ? nw * WIN * (K > 0 ? K : 1) * 8 : 0;
   return sa + scat + wsum + 16 * 8 + 16 * MAX_DOTS * 4 + MAX_DOTS * 8 + MAX_DOTS * 4 + (4 + MAX_DOTS) * 4;
 }
 
@@ -107,8 +111,8 @@ template <int N>
 struct Shm {
   long long* sa;    // K * SA_D    long accumulators (rare path)
   long long* wsa;   // nw * SA_D   row fallback accumulators (aliases scat)
-  long long* scat;  // nw * rows * WIN scatter rows
-  long long* wsum;  // 16 * K * WIN  per-wave window sums (lightweight: 16 * K * LW_REC doubles)
+  long long* scat;  // nw * rows * ROW_STRIDE scatter rows
+  long long* wsum;  // nw * K * WIN  per-wave window sums (lightweight: nw * K * LW_REC doubles)
   double* pbuf;     // 16          plain per-wave sums
   int* imax;        // 16 * MAX_DOTS per-wave maxima
   double* res;      // MAX_DOTS
@@ -126,9 +130,9 @@ __device__ __forceinline__ Shm<N> shm_carve(char* base, int K, bool rows) {
   off += (N > 0 && N != LW8) ? (size_t)K * SA_D * 8 : 0;
   s.scat = (long long*)(base + off);
   s.wsa = s.scat;
-  off += (N > 0) ? nw * scat_rows(blockDim.x) * WIN * 8 : 0;
+  off += (N > 0) ? nw * scat_rows(blockDim.x) * ROW_STRIDE * 8 : 0;
   s.wsum = (long long*)(base + off);
-  off += (N > 0) ? (size_t)16 * WIN * (K > 0 ? K : 1) * 8 : 0;
+  off += (N > 0) ? nw * WIN * (K > 0 ? K : 1) * 8 : 0;
   s.pbuf = (double*)(base + off);
   off += 16 * 8;
   s.imax = (int*)(base + off);
@@ -521,12 +525,18 @@ __device__ __forceinline__ double rows_wave_hat(const Csr& A, const double* __re
 // Exact workgroup reduction of one dot product into a window record
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const int o = __shfl_xor(v, off, 64);
-    v = (o > v) ? o : v;
-  }
-  return v;
+  // DPP within rows of 16 lanes (shifts 1, 2, 3, then 4 and 8 on the upper
+  // banks), then the row broadcasts of lanes 15 and 31: lane 63 ends with the
+  // maximum.  Lanes a step does not write keep INT_MIN, which max ignores.
+  constexpr int lo = -2147483647 - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x113, 0xf, 0xf, false));  // row_shr:3
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xe, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xc, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Block-wide max of v (all threads get it).  Uses s.imax; ends with a barrier.
@@ -561,58 +571,91 @@ __device__ __forceinline__ void block_max_k(int (&v)[K], const Shm<N>& s) {
   __syncthreads();
 }
 
-// Add the exact value of c (a double) to a private digit row whose digit 0 is grid
-// digit d0; digits below d0 go to the long accumulator `sa`.
-__device__ __forceinline__ void row_deposit(long long* row, int d0, double c, long long* sa, int* flag) {
-  if (c == 0.0) return;
-  bool neg;
-  unsigned long long m;
-  int e;
-  decode(c, neg, m, e);
-  const int pos = e - SA_LSB;
-  const int d = pos >> 5, sh = pos & 31;
-  const unsigned long long w0 = m << sh;
-  const unsigned long long w1 = sh ? (m >> (64 - sh)) : 0ull;
-  const unsigned int ch[3] = {(unsigned int)w0, (unsigned int)(w0 >> 32), (unsigned int)w1};
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    if (ch[j]) {
-      const long long v = neg ? -(long long)ch[j] : (long long)ch[j];
-      const int idx = d + j - d0;
-      if (idx >= 0) {
-        row[idx] += v;
-      } else {
-        atomicAdd((unsigned long long*)&sa[d + j], (unsigned long long)v);
-        atomicOr(flag, F_SA);
-      }
-    }
-  }
+// The exact value of a finite double c as three digit values on the long-
+// accumulator grid: c = D[0] G(d) + D[1] G(d+1) + D[2] G(d+2) with G(k) =
+// 2^(32 k + SA_LSB) and d the returned digit, taken from the two's complement of
+// the signed significand shifted into place, so D[0], D[1] lie in [0, 2^32) and
+// D[2] = floor(value / G(d+2)) is small and signed; c = +-0 gives three zeros.
+// d depends only on the exponent field, so it never decreases with |c|.
+__device__ __forceinline__ int digits3(double c, long long (&D)[3]) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(c);
+  const int ex = (int)((b >> 52) & 0x7ffull);
+  const unsigned long long m = (b & ((1ull << 52) - 1ull)) | ((unsigned long long)(ex != 0) << 52);
+  const long long sm = (b >> 63) ? -(long long)m : (long long)m;
+  const int pos = (ex > 1 ? ex : 1) - 1075 - SA_LSB;  // grid bit of the significand's last place
+  const int sh = pos & 31;
+  const unsigned long long lo = (unsigned long long)sm << sh;
+  D[0] = (long long)(lo & 0xffffffffull);
+  D[1] = (long long)(lo >> 32);
+  D[2] = (sm >> 32) >> (32 - sh);  // floor(sm 2^sh / 2^64): shifts of 32 + (32 - sh) bits
+  return pos >> 5;
 }
 
-// Wavefront part of the window reduction of one dot: every lane adds its FPE
-// components into a private LDS row of WIN digits (digit 0 = grid digit d0;
-// lower digits go to the long accumulator `sa`), then the rows are summed
-// column-wise (4 lanes per column, combined with shuffles).  Returns the
+// The highest grid digit that digits3 gives a non-zero value for any double of
+// magnitude at most |c| (c != 0).
+__device__ __forceinline__ int digits3_top(double c) {
+  const int ex = (int)(((unsigned long long)__double_as_longlong(c) >> 52) & 0x7ffull);
+  return (((ex > 1 ? ex : 1) - 1075 - SA_LSB) >> 5) + 2;
+}
+
+__device__ __forceinline__ void lds_add(long long* p, long long v) {
+  __hip_atomic_fetch_add((unsigned long long*)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wavefront part of the window reduction of one dot: every lane adds the
+// digits3 values of its FPE components into a private LDS row of WIN digits
+// (digit 0 = grid digit d0; d0 + WIN - 1 is at or above every component's top
+// digit; digits below d0 go to the long accumulator `sa`), then the rows are
+// summed column-wise (4 lanes per column, combined with shuffles).  Returns the
 // wavefront's sum of window digit `lane` in lanes 0..WIN-1.
 template <int N>
 __device__ __forceinline__ long long wave_window(const Fpe<N>& f, int d0, const Shm<N>& s, long long* sa, int* flag) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int rows = scat_rows(blockDim.x), quarter = rows / 4;
-  long long* R = s.scat + (size_t)w * rows * WIN;
-  const int col = lane % WIN, part = lane / WIN;  // lanes < 4*WIN: column, row quarter
+  const int rows = scat_rows(blockDim.x);
+  long long* R = s.scat + (size_t)w * rows * ROW_STRIDE;
+  const int col = lane % WIN, part = lane / WIN;  // lanes < 4*WIN: column, every 4th row from `part`
   long long colsum = 0;
   for (int q = 0; q < 64 / rows; ++q) {
     if (lane / rows == q) {
-      long long* row = R + (lane % rows) * WIN;
+      long long* row = R + (lane % rows) * ROW_STRIDE;
 #pragma unroll
       for (int i = 0; i < WIN; ++i) row[i] = 0;
+      bool below = false;
 #pragma unroll
-      for (int k = 0; k < N; ++k) row_deposit(row, d0, f.c[k], sa, flag);
+      for (int k = 0; k < N; ++k) {
+        long long D[3];
+        int idx = digits3(f.c[k], D) - d0;
+        if (f.c[k] == 0.0) idx = 0;  // three zeros, added anywhere in the row
+        if (idx >= 0) {
+#pragma unroll
+          for (int j = 0; j < 3; ++j) lds_add(row + idx + j, D[j]);
+        } else {
+          below = true;
+        }
+      }
+      if (below) {  // rare: components whose low digits lie below the window
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          long long D[3];
+          const int dg = digits3(f.c[k], D);
+          if (f.c[k] == 0.0 || dg >= d0) continue;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            if (dg + j >= d0) {
+              lds_add(row + (dg + j - d0), D[j]);
+            } else if (D[j] != 0) {
+              lds_add(sa + dg + j, D[j]);
+              atomicOr(flag, F_SA);
+            }
+          }
+        }
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (lane < 4 * WIN)
-      for (int r = part * quarter; r < (part + 1) * quarter; ++r) colsum += R[r * WIN + col];
+      for (int r = part; r < rows; r += 4) colsum += R[r * ROW_STRIDE + col];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
   }
@@ -712,7 +755,7 @@ __device__ __forceinline__ unsigned long long block_publish(Dot<N> (&d)[K], cons
       double mx = 0.0;
 #pragma unroll
       for (int k = 0; k < N; ++k) mx = fmax(mx, fabs(d[j].f.c[k]));
-      top[j] = (mx != 0.0) ? top_digit(mx) : -1;
+      top[j] = (mx != 0.0) ? digits3_top(mx) : -1;
     }
     block_max_k<N, K>(top, s);
 #pragma unroll
