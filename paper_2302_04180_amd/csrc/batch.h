@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, 
       st->varsigma = 0.0; st->zeta = 0.0;
       st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
       st->variant = variant; st->resumable = 0; st->lost = 0; st->spmv_go = 0;
+      st->rho_n = 0.0; st->pend = 0; st->iter_n = 0;
     }
   }
 }
@@ -142,7 +143,10 @@ __global__ void __launch_bounds__(1024) kb_std_A(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_A_body<Far, Unif>(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) {
+                          const State* st = D.V.st;
+                          std_A_body<Far, Unif>(D.A, D.V, R, st->beta, st->omega, st->iter > 0);
+                        });
 }
 
 template <int N, bool Unif>
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(1024) kb_std_B(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   tile_loop<N, 1, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_B_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
+    std_B_body<N, Unif, false>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -159,7 +163,7 @@ __global__ void __launch_bounds__(1024) kb_std_C(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { std_C_body<Far, Unif>(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { std_C_body<Far, Unif>(D.A, D.V, R, D.V.st->alpha); });
 }
 
 template <int N, bool Unif>
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(1024) kb_std_D(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_D_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
+    std_D_body<N, Unif, false>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -176,7 +180,8 @@ __global__ void __launch_bounds__(1024) kb_std_E(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    std_E_body<N, Far, Unif>(D.A, D.V, D.red, R, rec, s);
+    const State* st = D.V.st;
+    std_E_body<N, Far, Unif, false>(D.A, D.V, D.red, R, rec, s, st->alpha, st->omega, st->iter);
   });
 }
 

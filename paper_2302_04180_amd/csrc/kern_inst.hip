@@ -49,11 +49,12 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
     // vector; x and r0 in the Unif path); A.unif: p^ and q^ formed where read
     const bool far = V.far != 0;
     const size_t s1 = shm_bytes(N, 1, true, B), s2 = shm_bytes(N, 2, true, B), s2e = shm_bytes(N, 2, false, B);
+    const size_t s1e = shm_bytes(N, 1, false, B);
     if (A.unif) {
       switch (ph) {
-        case 0: return launch(k_std_A<N, false, true>, G, B, 0, s, A, V);
+        case 0: return launch(k_std_A<N, false, true>, G, B, s2e, s, A, V, red);
         case 1: return launch(k_std_B<N, true>, G, B, s1, s, A, V, red);
-        case 2: return launch(k_std_C<N, false, true>, G, B, 0, s, A, V);
+        case 2: return launch(k_std_C<N, false, true>, G, B, s1e, s, A, V, red);
         case 3: return launch(k_std_D<N, true>, G, B, s2, s, A, V, red);
         default:
           return far ? launch(k_std_E<N, true, true>, G, B, s2e, s, A, V, red)
@@ -62,12 +63,12 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
     }
     switch (ph) {
       case 0:
-        return far ? launch(k_std_A<N, true, false>, G, B, 0, s, A, V)
-                   : launch(k_std_A<N, false, false>, G, B, 0, s, A, V);
+        return far ? launch(k_std_A<N, true, false>, G, B, s2e, s, A, V, red)
+                   : launch(k_std_A<N, false, false>, G, B, s2e, s, A, V, red);
       case 1: return launch(k_std_B<N, false>, G, B, s1, s, A, V, red);
       case 2:
-        return far ? launch(k_std_C<N, true, false>, G, B, 0, s, A, V)
-                   : launch(k_std_C<N, false, false>, G, B, 0, s, A, V);
+        return far ? launch(k_std_C<N, true, false>, G, B, s1e, s, A, V, red)
+                   : launch(k_std_C<N, false, false>, G, B, s1e, s, A, V, red);
       case 3: return launch(k_std_D<N, false>, G, B, s2, s, A, V, red);
       default:
         return far ? launch(k_std_E<N, true, false>, G, B, s2e, s, A, V, red)
@@ -147,6 +148,7 @@ rpk_status KernB<N>::phase(int variant, int ph, int G, int Gf, int B, hipStream_
   (void)Gf;
   if (variant == RPK_STD) {
     const size_t s1 = shm_bytes(N, 1, true, B), s2 = shm_bytes(N, 2, true, B), s2e = shm_bytes(N, 2, false, B);
+    const size_t s1e = shm_bytes(N, 1, false, B);
     if (b.unif) {
       switch (ph) {
         case 0: return launch(kb_std_A<N, false, true>, G, B, 0, s, b);

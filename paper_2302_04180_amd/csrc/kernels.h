@@ -72,10 +72,13 @@ struct Csr {
 struct State {
   double alpha, omega, beta, rho, tau, tau0, tol, true_res;
   double varsigma, zeta;  // pipelined: <r0,s>, <r0,z> of the current iteration (S16, taken in P1)
+  double rho_n;           // standard loop, deferred reductions: rho after S10, moved to rho by B
   int iter, maxit, done, status;
   int variant, resumable;
   int lost;     // lightweight mode: dot products that could not keep every bit
   int spmv_go;  // pipelined: 1 when the kernel before an SpMV ran (written by that kernel only)
+  int pend;     // standard loop, deferred reductions: E published S10/S11 and A has not taken them
+  int iter_n;   // standard loop, deferred reductions: iter after S10, moved to iter by B
 };
 
 // Reduction scratch in the caller's workspace (left zeroed after every use).
@@ -829,10 +832,15 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
   return s.misc[10] != 0;
 }
 
-// In the last workgroup: round the K dots of slots slot0.. into s.res[0..K-1],
-// leaving the accumulators, flags (and plain slots) for the next use.
-template <int N, int K>
-__device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& red, int slot0) {
+// Round the K dots of slots slot0.. into s.res[0..K-1] (their flags into
+// s.misc[1..K]).  Clear (the last workgroup to arrive): read the exact
+// accumulators and flags with exchanges that leave them zeroed for the next use.
+// !Clear (every workgroup of the kernel after the one that published, exact and
+// plain dots only): read them with device-scope loads and leave them; a later
+// kernel clears them (block_clear_slots).
+template <int N, int K, bool Clear = true>
+__device__ __forceinline__ void block_finalize(const Shm<N>& s, const Red& red, int slot0) {
+  static_assert(Clear || N != LW8, "lightweight records are always finished by the last workgroup");
   const int tid = threadIdx.x, bd = blockDim.x;
   if constexpr (N == LW8) {
     const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
@@ -870,12 +878,14 @@ __device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& 
     __syncthreads();
   } else if constexpr (N > 0) {
     for (int i = tid; i < K * SA_D; i += bd) {
-      const int j = i / SA_D, k = i - j * SA_D;
-      s.sa[i] = (long long)__hip_atomic_exchange((unsigned long long*)&red.gsa[(size_t)(slot0 + j) * SA_D + k], 0ull,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long* g = (unsigned long long*)&red.gsa[(size_t)slot0 * SA_D + i];
+      s.sa[i] = Clear ? (long long)__hip_atomic_exchange(g, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : (long long)__hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid < K)
-      s.misc[1 + tid] = __hip_atomic_exchange(&red.gflags[slot0 + tid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s.misc[1 + tid] = Clear ? __hip_atomic_exchange(&red.gflags[slot0 + tid], 0, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                              : __hip_atomic_load(&red.gflags[slot0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
     for (int j = w; j < K; j += nw) {  // one wave per dot
@@ -913,6 +923,25 @@ __device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& 
       if (tid == 0) s.res[j] = t;
     }
     __syncthreads();
+  }
+}
+
+template <int N, int K>
+__device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& red, int slot0) {
+  block_finalize<N, K, true>(s, red, slot0);
+}
+
+// Zero the exact accumulators and flags of slots slot0..slot0+K-1 (one
+// workgroup; device-scope stores, so the atomics of a later kernel see them).
+// Plain slots need nothing: every publication overwrites them.
+template <int N, int K>
+__device__ __forceinline__ void block_clear_slots(const Red& red, int slot0) {
+  if constexpr (N > 0 && N != LW8) {
+    for (int i = threadIdx.x; i < K * SA_D; i += blockDim.x)
+      __hip_atomic_store((unsigned long long*)&red.gsa[(size_t)slot0 * SA_D + i], 0ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < K)
+      __hip_atomic_store(&red.gflags[slot0 + threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

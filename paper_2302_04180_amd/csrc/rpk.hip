@@ -588,7 +588,9 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
     int chunk = c.graph > 0 ? c.graph : 4;
     long long launched = 0;
     while (!g_pinned->done) {
-      if (launched > (long long)o->maxit + 8) { st = RPK_ERR_HIP; break; }  // cannot happen: device stops at maxit
+      // cannot happen: the device stops at maxit, in the first kernel of the
+      // chunk after the one that ran the last iteration at the latest
+      if (launched > (long long)o->maxit + 8) { st = RPK_ERR_HIP; break; }
       if (timing) {
         for (int ph = 0; ph < nph && st == RPK_OK; ++ph) {
           if (hipEventRecord(ev[ph], s) != hipSuccess) st = RPK_ERR_HIP;

@@ -76,6 +76,7 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.varsigma = s->varsigma; d.zeta = s->zeta;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
   d.variant = s->variant; d.resumable = s->resumable; d.lost = s->lost; d.spmv_go = 0;
+  d.rho_n = 0.0; d.pend = 0; d.iter_n = 0;
 }
 
 __device__ __forceinline__ void state_store(State* d, const State& s) {
@@ -326,6 +327,82 @@ __device__ __forceinline__ void publish_or_defer(Dot<N> (&d)[K], const Shm<N>& s
   else publish_step<N, K, F>(d, s, V, red, rec);
 }
 
+// Deferred reduction points of the standard loop (single solves, exact and
+// plain dots).  The kernel that produces a point's terms only publishes them,
+// with neither an arrival count nor a last workgroup; every workgroup of the
+// kernel that needs the result rounds the dots itself from the published
+// accumulators (block_finalize without clearing) and takes the scalar step on
+// its own copy of the state, so a reduction point costs a few loads at the
+// start of that kernel instead of two device-wide round trips and a serial
+// rounding at the end of the kernel before it.  All copies compute the same
+// bits.  Workgroup 0 stores what the step decided, only into fields that no
+// workgroup of the same kernel reads: S10/S11 leave iter and rho in iter_n and
+// rho_n, which B moves.  The slots are cleared two kernels after their
+// publication: D clears B's, A clears D's, B clears E's.
+constexpr int SLOT_SIGMA = 0;  // B: <r0,s>
+constexpr int SLOT_THETA = 1;  // D: <q,y>, <y,y>
+constexpr int SLOT_RHO = 3;    // E: <r0,r>, <r,r>
+
+template <int N>
+constexpr bool defer_std() {
+  return N != LW8;
+}
+
+// done | pend << 1, read once per workgroup so that all its threads take the
+// same branch while workgroup 0 of the same kernel may store done.
+template <int N>
+__device__ __forceinline__ int wg_flags(const Shm<N>& s, const State* st) {
+  if (threadIdx.x == 0) s.misc[9] = st->done | (st->pend << 1);
+  __syncthreads();
+  const int f = s.misc[9];
+  __syncthreads();
+  return f;
+}
+
+// Round the K dots of slots slot0.. and take step F (S3: alpha, S7: omega,
+// S10/S11: tau, stop test, beta) on a private state; returns, in every thread,
+// whether the step stopped the solve, and the step's scalar in `out`.
+template <int N, int K, int F>
+__device__ __forceinline__ bool consume_step(const Shm<N>& s, const Vecs& V, const Red& red, int slot0,
+                                             double& out) {
+  block_finalize<N, K, false>(s, red, slot0);
+  if (threadIdx.x == 0) {
+    State S;
+    state_load(S, V.st);
+    State* st = V.st;
+    const bool w0 = blockIdx.x == 0;
+    double* h = w0 ? hist_row(V, S.iter) : nullptr;
+    if constexpr (F == FIN_ALPHA) {
+      step_std_alpha(&S, h, s.res[0]);
+      s.res[MAX_DOTS - 1] = S.alpha;
+      if (w0) st->alpha = S.alpha;
+    } else if constexpr (F == FIN_OMEGA) {
+      step_omega(&S, h, s.res[0], s.res[1], 2);
+      s.res[MAX_DOTS - 1] = S.omega;
+      if (w0) st->omega = S.omega;
+    } else {
+      static_assert(F == FIN_BETA, "deferred points: S3, S7, S10/S11");
+      step_std_beta(&S, h, s.res[0], s.res[1]);
+      s.res[MAX_DOTS - 1] = S.beta;
+      if (w0) {
+        st->beta = S.beta;
+        st->tau = S.tau;
+        st->resumable = S.resumable;
+        st->rho_n = S.rho;
+        st->iter_n = S.iter;
+      }
+    }
+    if (w0 && S.done) {
+      st->status = S.status;
+      st->done = 1;
+    }
+    s.misc[9] = S.done;
+  }
+  __syncthreads();
+  out = s.res[MAX_DOTS - 1];
+  return s.misc[9] != 0;
+}
+
 // ---------------------------------------------------------------------------
 // Phase bodies.  Each works on the rows [R.lo, R.hi) of one system (R.lo a
 // multiple of 64) and publishes its dot partials as record `rec` of that
@@ -380,10 +457,8 @@ __device__ __forceinline__ void st_far(double* p, double v) { st_v<true>(p, v); 
 // A: S12 (iterations after the first) and S1 (not stored for a uniform Jacobi
 // vector: B and E form p^ themselves)
 template <bool Far, bool Unif>
-__device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R) {
-  const State* st = V.st;
-  const bool upd = st->iter > 0;
-  const double beta = st->beta, omega = st->omega;
+__device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R, double beta, double omega,
+                                           bool upd) {
   if constexpr (Unif) {
     if (!upd) return;  // p = r0 from the set-up
     for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
@@ -426,7 +501,7 @@ __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R)
 }
 
 // B: S2 + S3 partial
-template <int N, bool Unif>
+template <int N, bool Unif, bool Defer>
 __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s) {
   Dot<N> d[1];
@@ -441,13 +516,13 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
       d[0].add(r0, si, s.sa, &s.flag[0]);
     }
   }
-  publish_step<N, 1, FIN_ALPHA>(d, s, V, red, rec);
+  if constexpr (Defer) (void)block_publish<N, 1>(d, s, red, SLOT_SIGMA, rec);
+  else publish_step<N, 1, FIN_ALPHA>(d, s, V, red, rec);
 }
 
 // C: S4 + S5 (S5 not stored for a uniform Jacobi vector: D and E form q^)
 template <bool Far, bool Unif>
-__device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R) {
-  const double alpha = V.st->alpha;
+__device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R, double alpha) {
   if constexpr (Unif) {
     for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
       const int i1 = i0 + blockDim.x;
@@ -477,7 +552,7 @@ __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R)
 }
 
 // D: S6 + S7 partials
-template <int N, bool Unif>
+template <int N, bool Unif, bool Defer>
 __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s) {
   Dot<N> d[2];
@@ -494,16 +569,16 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
       d[1].add(yi, yi, s.sa + SA_D, &s.flag[1]);
     }
   }
-  publish_step<N, 2, FIN_OMEGA>(d, s, V, red, rec);
+  if constexpr (Defer) (void)block_publish<N, 2>(d, s, red, SLOT_THETA, rec);
+  else publish_step<N, 2, FIN_OMEGA>(d, s, V, red, rec);
 }
 
 // E: S8 + S9 + S10/S11 partials.  Unif: p^ = RN(du p) and q^ = RN(du q) are
 // formed here from p and q (q is read for S9 anyway).
 template <int N, bool Far, bool Unif>
-__device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R, Dot<N> (&d)[2], const Shm<N>& s) {
-  const State* st = V.st;
-  const double alpha = st->alpha, omega = st->omega, du = A.du;
-  const int iter = st->iter;
+__device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R, Dot<N> (&d)[2], const Shm<N>& s,
+                                           double alpha, double omega, int iter) {
+  const double du = A.du;
   // two rows per step, every load issued before any store
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
     const int i1 = i0 + blockDim.x;
@@ -542,14 +617,15 @@ __device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R,
   }
 }
 
-template <int N, bool Far, bool Unif>
+template <int N, bool Far, bool Unif, bool Defer>
 __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
-                                           const Shm<N>& s) {
+                                           const Shm<N>& s, double alpha, double omega, int iter) {
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
-  std_E_rows<N, Far, Unif>(A, V, R, d, s);
-  publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
+  std_E_rows<N, Far, Unif>(A, V, R, d, s, alpha, omega, iter);
+  if constexpr (Defer) (void)block_publish<N, 2>(d, s, red, SLOT_RHO, rec);
+  else publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
 }
 
 // true residual ||b - A x|| (reported at exit): partial <e, e> (slot 0)
@@ -807,43 +883,94 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
   std_init_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
+// Single solves with exact or plain dots take the standard loop's reduction
+// points deferred (consume_step); lightweight dots keep the last-workgroup
+// finish, which merges the workgroups' FPE records once rather than in every
+// workgroup.
 template <int N, bool Far, bool Unif>
-__global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V) {
-  if (V.st->done) return;
-  std_A_body<Far, Unif>(A, V, my_rows(A.n));
+__global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>()) {
+    extern __shared__ __align__(16) char smem[];
+    Shm<N> s = shm_carve<N>(smem, 2, false);
+    if (blockIdx.x == 0) block_clear_slots<N, 2>(red, SLOT_THETA);
+    const int fl = wg_flags(s, V.st);
+    if (fl & 1) return;
+    double beta = V.st->beta;
+    bool upd = V.st->iter > 0;
+    if (fl & 2) {  // S10, S11 and the stop test, on the dots E published
+      if (consume_step<N, 2, FIN_BETA>(s, V, red, SLOT_RHO, beta)) return;
+      upd = true;
+    }
+    std_A_body<Far, Unif>(A, V, my_rows(A.n), beta, V.st->omega, upd);
+  } else {
+    const State* st = V.st;
+    if (st->done) return;
+    std_A_body<Far, Unif>(A, V, my_rows(A.n), st->beta, st->omega, st->iter > 0);
+  }
 }
 
 template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>()) {
+    if (blockIdx.x == 0) {  // A has taken E's dots: clear them, move iter and rho
+      block_clear_slots<N, 2>(red, SLOT_RHO);
+      if (threadIdx.x == 0 && V.st->pend) {
+        V.st->iter = V.st->iter_n;
+        V.st->rho = V.st->rho_n;
+        V.st->pend = 0;
+      }
+    }
+  }
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   shm_init(s, 1);
-  std_B_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_B_body<N, Unif, defer_std<N>()>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N, bool Far, bool Unif>
-__global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V) {
-  if (V.st->done) return;
-  std_C_body<Far, Unif>(A, V, my_rows(A.n));
+__global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>()) {
+    extern __shared__ __align__(16) char smem[];
+    Shm<N> s = shm_carve<N>(smem, 1, false);
+    if (wg_flags(s, V.st) & 1) return;
+    double alpha;
+    if (consume_step<N, 1, FIN_ALPHA>(s, V, red, SLOT_SIGMA, alpha)) return;  // S3
+    std_C_body<Far, Unif>(A, V, my_rows(A.n), alpha);
+  } else {
+    if (V.st->done) return;
+    std_C_body<Far, Unif>(A, V, my_rows(A.n), V.st->alpha);
+  }
 }
 
 template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_D(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>())
+    if (blockIdx.x == 0) block_clear_slots<N, 1>(red, SLOT_SIGMA);  // C has taken B's dot
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, true);
   shm_init(s, 2);
-  std_D_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  std_D_body<N, Unif, defer_std<N>()>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
-  shm_init(s, 2);
-  std_E_body<N, Far, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  if constexpr (defer_std<N>()) {
+    if (wg_flags(s, V.st) & 1) return;
+    double omega;
+    if (consume_step<N, 2, FIN_OMEGA>(s, V, red, SLOT_THETA, omega)) return;  // S7
+    shm_init(s, 2);
+    std_E_body<N, Far, Unif, true>(A, V, red, my_rows(A.n), blockIdx.x, s, V.st->alpha, omega, V.st->iter);
+    if (threadIdx.x == 0) V.st->pend = 1;
+  } else {
+    const State* st = V.st;
+    if (st->done) return;
+    shm_init(s, 2);
+    std_E_body<N, Far, Unif, false>(A, V, red, my_rows(A.n), blockIdx.x, s, st->alpha, st->omega, st->iter);
+  }
 }
 
 template <int N>
