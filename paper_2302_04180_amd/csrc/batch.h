@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(1024) kb_std_E(Batch B) {
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
     const State* st = D.V.st;
-    std_E_body<N, Far, Unif, false>(D.A, D.V, D.red, R, rec, s, st->alpha, st->omega, st->iter);
+    std_E_body<N, Far, Unif>(D.A, D.V, D.red, R, rec, s, st->alpha, st->omega, st->iter);
   });
 }
 

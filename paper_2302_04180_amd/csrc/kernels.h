@@ -832,6 +832,33 @@ __device__ __forceinline__ bool block_publish_last(Dot<N> (&d)[K], const Shm<N>&
   return s.misc[10] != 0;
 }
 
+// Exact dots: round the K long accumulators in s.sa (their flags in
+// s.misc[1..K]) into s.res[0..K-1]; one wavefront per dot.  All threads call it.
+template <int N, int K>
+__device__ __forceinline__ void block_round_sa(const Shm<N>& s) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
+  for (int j = w; j < K; j += nw) {  // one wave per dot
+    long long* tot = s.sa + (size_t)j * SA_D;
+    int lo, hi;
+    wave_digit_range(tot, SA_D, lo, hi);
+    double r = 0.0;
+    if (hi >= 0) {
+      constexpr int RW = 16;  // register window (digits) of the common case
+      const int start = (lo < SA_D - RW) ? lo : SA_D - RW;
+      if (hi + 2 <= start + RW - 1) {
+        if (lane == 0) r = window_round_reg<RW>(tot + start, start);
+      } else {
+        r = sa_round_wave(tot);
+      }
+    }
+    if (lane == 0) s.res[j] = r;
+  }
+  __syncthreads();
+  if (tid < K && (s.misc[1 + tid] & F_NONFINITE)) s.res[tid] = __longlong_as_double(0x7ff8000000000000ll);
+  __syncthreads();
+}
+
 // Round the K dots of slots slot0.. into s.res[0..K-1] (their flags into
 // s.misc[1..K]).  Clear (the last workgroup to arrive): read the exact
 // accumulators and flags with exchanges that leave them zeroed for the next use.
@@ -887,26 +914,7 @@ __device__ __forceinline__ void block_finalize(const Shm<N>& s, const Red& red, 
                                                       __HIP_MEMORY_SCOPE_AGENT)
                               : __hip_atomic_load(&red.gflags[slot0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const int nw = bd >> 6, w = tid >> 6, lane = tid & 63;
-    for (int j = w; j < K; j += nw) {  // one wave per dot
-      long long* tot = s.sa + (size_t)j * SA_D;
-      int lo, hi;
-      wave_digit_range(tot, SA_D, lo, hi);
-      double r = 0.0;
-      if (hi >= 0) {
-        constexpr int RW = 16;  // register window (digits) of the common case
-        const int start = (lo < SA_D - RW) ? lo : SA_D - RW;
-        if (hi + 2 <= start + RW - 1) {
-          if (lane == 0) r = window_round_reg<RW>(tot + start, start);
-        } else {
-          r = sa_round_wave(tot);
-        }
-      }
-      if (lane == 0) s.res[j] = r;
-    }
-    __syncthreads();
-    if (tid < K && (s.misc[1 + tid] & F_NONFINITE)) s.res[tid] = __longlong_as_double(0x7ff8000000000000ll);
-    __syncthreads();
+    block_round_sa<N, K>(s);
   } else {
     double v[K];
 #pragma unroll
@@ -944,6 +952,39 @@ __device__ __forceinline__ void block_clear_slots(const Red& red, int slot0) {
       __hip_atomic_store(&red.gflags[slot0 + threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
+
+// A reduction published by the kernel before (exact dots), read by every
+// workgroup of the next one: issue() starts the device-scope loads of the
+// digits and flags into registers, so that the caller can start its own loads
+// behind them; store() puts them in s.sa / s.misc[1..K] ahead of a barrier and
+// block_round_sa.
+constexpr int DCAP = (2 * SA_D + 63) / 64;  // digits per thread: K <= 2, at least 64 threads
+template <int N, int K>
+struct Published {
+  long long dg[DCAP];
+  int fl;
+  __device__ __forceinline__ void issue(const Red& red, int slot0) {
+    static_assert(K * SA_D <= DCAP * 64, "Published holds at most two dots");
+#pragma unroll
+    for (int r = 0; r < DCAP; ++r) {
+      const int i = threadIdx.x + r * blockDim.x;
+      dg[r] = (i < K * SA_D) ? (long long)__hip_atomic_load((unsigned long long*)&red.gsa[(size_t)slot0 * SA_D + i],
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : 0ll;
+    }
+    fl = (threadIdx.x < K) ? __hip_atomic_load(&red.gflags[slot0 + threadIdx.x], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : 0;
+  }
+  __device__ __forceinline__ void store(const Shm<N>& s) const {
+#pragma unroll
+    for (int r = 0; r < DCAP; ++r) {
+      const int i = threadIdx.x + r * blockDim.x;
+      if (i < K * SA_D) s.sa[i] = dg[r];
+    }
+    if (threadIdx.x < K) s.misc[1 + threadIdx.x] = fl;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Standalone exdot / plain dot and SpMV

@@ -331,10 +331,10 @@ __device__ __forceinline__ void publish_or_defer(Dot<N> (&d)[K], const Shm<N>& s
 // plain dots).  The kernel that produces a point's terms only publishes them,
 // with neither an arrival count nor a last workgroup; every workgroup of the
 // kernel that needs the result rounds the dots itself from the published
-// accumulators (block_finalize without clearing) and takes the scalar step on
-// its own copy of the state, so a reduction point costs a few loads at the
-// start of that kernel instead of two device-wide round trips and a serial
-// rounding at the end of the kernel before it.  All copies compute the same
+// accumulators (read, not cleared) and takes the scalar step on its own copy of
+// the state, while its first operands load, so a reduction point costs a
+// rounding at the start of that kernel instead of two device-wide round trips
+// and a serial rounding at the end of the kernel before it.  All copies compute the same
 // bits.  Workgroup 0 stores what the step decided, only into fields that no
 // workgroup of the same kernel reads: S10/S11 leave iter and rho in iter_n and
 // rho_n, which B moves.  The slots are cleared two kernels after their
@@ -348,60 +348,72 @@ constexpr bool defer_std() {
   return N != LW8;
 }
 
-// done | pend << 1, read once per workgroup so that all its threads take the
-// same branch while workgroup 0 of the same kernel may store done.
-template <int N>
-__device__ __forceinline__ int wg_flags(const Shm<N>& s, const State* st) {
-  if (threadIdx.x == 0) s.misc[9] = st->done | (st->pend << 1);
-  __syncthreads();
-  const int f = s.misc[9];
-  __syncthreads();
-  return f;
-}
-
-// Round the K dots of slots slot0.. and take step F (S3: alpha, S7: omega,
-// S10/S11: tau, stop test, beta) on a private state; returns, in every thread,
-// whether the step stopped the solve, and the step's scalar in `out`.
-template <int N, int K, int F>
-__device__ __forceinline__ bool consume_step(const Shm<N>& s, const Vecs& V, const Red& red, int slot0,
-                                             double& out) {
-  block_finalize<N, K, false>(s, red, slot0);
-  if (threadIdx.x == 0) {
-    State S;
-    state_load(S, V.st);
-    State* st = V.st;
-    const bool w0 = blockIdx.x == 0;
-    double* h = w0 ? hist_row(V, S.iter) : nullptr;
-    if constexpr (F == FIN_ALPHA) {
-      step_std_alpha(&S, h, s.res[0]);
-      s.res[MAX_DOTS - 1] = S.alpha;
-      if (w0) st->alpha = S.alpha;
-    } else if constexpr (F == FIN_OMEGA) {
-      step_omega(&S, h, s.res[0], s.res[1], 2);
-      s.res[MAX_DOTS - 1] = S.omega;
-      if (w0) st->omega = S.omega;
-    } else {
-      static_assert(F == FIN_BETA, "deferred points: S3, S7, S10/S11");
-      step_std_beta(&S, h, s.res[0], s.res[1]);
-      s.res[MAX_DOTS - 1] = S.beta;
-      if (w0) {
-        st->beta = S.beta;
-        st->tau = S.tau;
-        st->resumable = S.resumable;
-        st->rho_n = S.rho;
-        st->iter_n = S.iter;
-      }
+// One deferred point as seen by a workgroup of the kernel that needs it.
+// issue() starts the loads (the K published dots -- exact digits -- and, in
+// thread 0, the state) so that the caller can issue its own first loads behind
+// them; flags() returns done | pend << 1 of the state as loaded, the same in
+// every thread; step<F>() rounds the dots and takes step F (S3: alpha, S7: omega,
+// S10/S11: tau, stop test, beta) on the loaded state, and returns, in every
+// thread, whether the step stopped the solve, with the step's scalar in `out`.
+// The state may change under the kernel only in fields the step does not read,
+// or in done, which the step would set the same way.
+template <int N, int K>
+struct Deferred {
+  Published<N, K> pub;
+  State S;
+  int pend;
+  __device__ __forceinline__ void issue(const Red& red, int slot0, const State* st) {
+    if constexpr (N > 0) pub.issue(red, slot0);
+    if (threadIdx.x == 0) {
+      state_load(S, st);
+      pend = st->pend;
     }
-    if (w0 && S.done) {
-      st->status = S.status;
-      st->done = 1;
-    }
-    s.misc[9] = S.done;
   }
-  __syncthreads();
-  out = s.res[MAX_DOTS - 1];
-  return s.misc[9] != 0;
-}
+  __device__ __forceinline__ int flags(const Shm<N>& s) {
+    if constexpr (N > 0) pub.store(s);
+    if (threadIdx.x == 0) s.misc[9] = S.done | (pend << 1);
+    __syncthreads();
+    return s.misc[9];
+  }
+  template <int F>
+  __device__ __forceinline__ bool step(const Shm<N>& s, const Vecs& V, const Red& red, int slot0, double& out) {
+    if constexpr (N > 0) block_round_sa<N, K>(s);
+    else block_finalize<N, K, false>(s, red, slot0);
+    if (threadIdx.x == 0) {
+      State* st = V.st;
+      const bool w0 = blockIdx.x == 0;
+      double* h = w0 ? hist_row(V, S.iter) : nullptr;
+      if constexpr (F == FIN_ALPHA) {
+        step_std_alpha(&S, h, s.res[0]);
+        s.res[MAX_DOTS - 1] = S.alpha;
+        if (w0) st->alpha = S.alpha;
+      } else if constexpr (F == FIN_OMEGA) {
+        step_omega(&S, h, s.res[0], s.res[1], 2);
+        s.res[MAX_DOTS - 1] = S.omega;
+        if (w0) st->omega = S.omega;
+      } else {
+        static_assert(F == FIN_BETA, "deferred points: S3, S7, S10/S11");
+        step_std_beta(&S, h, s.res[0], s.res[1]);
+        s.res[MAX_DOTS - 1] = S.beta;
+        if (w0) {
+          st->beta = S.beta;
+          st->tau = S.tau;
+          st->resumable = S.resumable;
+          st->rho_n = S.rho;
+          st->iter_n = S.iter;
+        }
+      }
+      if (w0 && S.done) {
+        st->status = S.status;
+        st->done = 1;
+      }
+      s.misc[9] = S.done;
+    }
+    __syncthreads();
+    out = s.res[MAX_DOTS - 1];
+    return s.misc[9] != 0;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Phase bodies.  Each works on the rows [R.lo, R.hi) of one system (R.lo a
@@ -455,37 +467,34 @@ __device__ __forceinline__ double ld_far(const double* p) { return ld_v<true>(p)
 __device__ __forceinline__ void st_far(double* p, double v) { st_v<true>(p, v); }
 
 // A: S12 (iterations after the first) and S1 (not stored for a uniform Jacobi
-// vector: B and E form p^ themselves)
+// vector: B and E form p^ themselves), on the rows i0 and i1 = i0 + blockDim.x:
+// load() issues every load, run() the arithmetic and the stores (s and r are
+// loaded in the first iteration too, unused)
 template <bool Far, bool Unif>
-__device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R, double beta, double omega,
-                                           bool upd) {
-  if constexpr (Unif) {
-    if (!upd) return;  // p = r0 from the set-up
-    for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
-      const int i1 = i0 + blockDim.x;
-      const bool two = i1 < R.hi;
-      const int j1 = two ? i1 : i0;
-      const double p0 = V.p[i0], p1 = V.p[j1], s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
-      V.p[i0] = fma(beta, fma(-omega, s0, p0), r0);  // S12
-      if (two) V.p[i1] = fma(beta, fma(-omega, s1, p1), r1);
-    }
-    return;
-  }
-  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
-    const int i1 = i0 + blockDim.x;
-    const bool two = i1 < R.hi;
+struct RowsA {
+  int i0, i1;
+  bool two;
+  double p[2], s[2], r[2], d[2];
+  __device__ __forceinline__ void load(const Csr& A, const Vecs& V, int i, int hi) {
+    i0 = i;
+    i1 = i + blockDim.x;
+    two = i1 < hi;
     const int j1 = two ? i1 : i0;
-    double p[2], s[2], r[2], d[2];
-    p[0] = ld_v<Far>(&V.p[i0]);
-    p[1] = ld_v<Far>(&V.p[j1]);
-    d[0] = ld_v<Far>(&A.dinv[i0]);
-    d[1] = ld_v<Far>(&A.dinv[j1]);
-    if (upd) {
-      s[0] = V.s[i0];
-      s[1] = V.s[j1];
-      r[0] = V.r[i0];
-      r[1] = V.r[j1];
+    if constexpr (Unif) {
+      p[0] = V.p[i0];
+      p[1] = V.p[j1];
+    } else {
+      p[0] = ld_v<Far>(&V.p[i0]);
+      p[1] = ld_v<Far>(&V.p[j1]);
+      d[0] = ld_v<Far>(&A.dinv[i0]);
+      d[1] = ld_v<Far>(&A.dinv[j1]);
     }
+    s[0] = V.s[i0];
+    s[1] = V.s[j1];
+    r[0] = V.r[i0];
+    r[1] = V.r[j1];
+  }
+  __device__ __forceinline__ void run(const Vecs& V, double beta, double omega, bool upd) const {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (u == 1 && !two) break;
@@ -493,10 +502,23 @@ __device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R,
       double pv = p[u];
       if (upd) {
         pv = fma(beta, fma(-omega, s[u], pv), r[u]);  // S12
-        st_v<Far>(&V.p[i], pv);
+        if constexpr (Unif) V.p[i] = pv;
+        else st_v<Far>(&V.p[i], pv);
       }
-      V.ph[i] = d[u] * pv;  // S1
+      if constexpr (!Unif) V.ph[i] = d[u] * pv;  // S1
     }
+  }
+};
+
+template <bool Far, bool Unif>
+__device__ __forceinline__ void std_A_body(const Csr& A, const Vecs& V, Range R, double beta, double omega,
+                                           bool upd) {
+  if constexpr (Unif)
+    if (!upd) return;  // p = r0 from the set-up
+  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+    RowsA<Far, Unif> a;
+    a.load(A, V, i0, R.hi);
+    a.run(V, beta, omega, upd);
   }
 }
 
@@ -520,34 +542,45 @@ __device__ __forceinline__ void std_B_body(const Csr& A, const Vecs& V, const Re
   else publish_step<N, 1, FIN_ALPHA>(d, s, V, red, rec);
 }
 
-// C: S4 + S5 (S5 not stored for a uniform Jacobi vector: D and E form q^)
+// C: S4 + S5 (S5 not stored for a uniform Jacobi vector: D and E form q^), on
+// the rows i0 and i1 = i0 + blockDim.x
+template <bool Far, bool Unif>
+struct RowsC {
+  int i0, i1;
+  bool two;
+  double s[2], r[2], d[2];
+  __device__ __forceinline__ void load(const Csr& A, const Vecs& V, int i, int hi) {
+    i0 = i;
+    i1 = i + blockDim.x;
+    two = i1 < hi;
+    const int j1 = two ? i1 : i0;
+    s[0] = V.s[i0];
+    s[1] = V.s[j1];
+    r[0] = V.r[i0];
+    r[1] = V.r[j1];
+    if constexpr (!Unif) {
+      d[0] = ld_v<Far>(&A.dinv[i0]);
+      d[1] = ld_v<Far>(&A.dinv[j1]);
+    }
+  }
+  __device__ __forceinline__ void run(const Vecs& V, double alpha) const {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
+      const int i = u ? i1 : i0;
+      const double q = fma(-alpha, s[u], r[u]);  // S4
+      V.q[i] = q;
+      if constexpr (!Unif) V.qh[i] = d[u] * q;  // S5
+    }
+  }
+};
+
 template <bool Far, bool Unif>
 __device__ __forceinline__ void std_C_body(const Csr& A, const Vecs& V, Range R, double alpha) {
-  if constexpr (Unif) {
-    for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
-      const int i1 = i0 + blockDim.x;
-      const bool two = i1 < R.hi;
-      const int j1 = two ? i1 : i0;
-      const double s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
-      V.q[i0] = fma(-alpha, s0, r0);  // S4
-      if (two) V.q[i1] = fma(-alpha, s1, r1);
-    }
-    return;
-  }
   for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
-    const int i1 = i0 + blockDim.x;
-    const bool two = i1 < R.hi;
-    const int j1 = two ? i1 : i0;
-    const double s0 = V.s[i0], s1 = V.s[j1], r0 = V.r[i0], r1 = V.r[j1];
-    const double d0 = ld_v<Far>(&A.dinv[i0]), d1 = ld_v<Far>(&A.dinv[j1]);
-    const double q0 = fma(-alpha, s0, r0);  // S4
-    V.q[i0] = q0;
-    V.qh[i0] = d0 * q0;                     // S5
-    if (two) {
-      const double q1 = fma(-alpha, s1, r1);
-      V.q[i1] = q1;
-      V.qh[i1] = d1 * q1;
-    }
+    RowsC<Far, Unif> c;
+    c.load(A, V, i0, R.hi);
+    c.run(V, alpha);
   }
 }
 
@@ -573,38 +606,42 @@ __device__ __forceinline__ void std_D_body(const Csr& A, const Vecs& V, const Re
   else publish_step<N, 2, FIN_OMEGA>(d, s, V, red, rec);
 }
 
-// E: S8 + S9 + S10/S11 partials.  Unif: p^ = RN(du p) and q^ = RN(du q) are
-// formed here from p and q (q is read for S9 anyway).
+// E: S8 + S9 + S10/S11 partials on the rows i0 and i1 = i0 + blockDim.x.  Unif:
+// p^ = RN(du p) and q^ = RN(du q) are formed here from p and q (q is read for S9
+// anyway).
 template <int N, bool Far, bool Unif>
-__device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R, Dot<N> (&d)[2], const Shm<N>& s,
-                                           double alpha, double omega, int iter) {
-  const double du = A.du;
-  // two rows per step, every load issued before any store
-  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
-    const int i1 = i0 + blockDim.x;
-    const bool two = i1 < R.hi;
-    double qh[2], ph[2], xo[2], y[2], q[2], r0[2];
+struct RowsE {
+  int i0, i1;
+  bool two;
+  double qh[2], ph[2], xo[2], y[2], q[2], r0[2];
+  __device__ __forceinline__ void load(const Vecs& V, int i, int hi) {
+    i0 = i;
+    i1 = i + blockDim.x;
+    two = i1 < hi;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int i = u ? (two ? i1 : i0) : i0;
+    for (int u = 0; u < 2; ++u) {  // every load issued before any store
+      const int j = u ? (two ? i1 : i0) : i0;
       if constexpr (Unif) {
-        ph[u] = V.p[i];
+        ph[u] = V.p[j];
       } else {
-        qh[u] = V.qh[i];
-        ph[u] = V.ph[i];
+        qh[u] = V.qh[j];
+        ph[u] = V.ph[j];
       }
-      xo[u] = ld_v<Far>(&V.x[i]);
-      y[u] = V.y[i];
-      q[u] = V.q[i];
-      r0[u] = ld_v<Far>(&V.r0[i]);
+      xo[u] = ld_v<Far>(&V.x[j]);
+      y[u] = V.y[j];
+      q[u] = V.q[j];
+      r0[u] = ld_v<Far>(&V.r0[j]);
     }
+  }
+  __device__ __forceinline__ void run(const Csr& A, const Vecs& V, Dot<N> (&d)[2], const Shm<N>& s, double alpha,
+                                      double omega, int iter) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (u == 1 && !two) break;
       const int i = u ? i1 : i0;
       if constexpr (Unif) {
-        ph[u] = du * ph[u];  // S1
-        qh[u] = du * q[u];   // S5
+        ph[u] = A.du * ph[u];  // S1
+        qh[u] = A.du * q[u];   // S5
       }
       const double x = fma(omega, qh[u], fma(alpha, ph[u], xo[u]));  // S8
       const double r = fma(-omega, y[u], q[u]);                       // S9
@@ -615,17 +652,26 @@ __device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R,
       d[1].add(r, r, s.sa + SA_D, &s.flag[1]);                        // S11
     }
   }
+};
+
+template <int N, bool Far, bool Unif>
+__device__ __forceinline__ void std_E_rows(const Csr& A, const Vecs& V, Range R, Dot<N> (&d)[2], const Shm<N>& s,
+                                           double alpha, double omega, int iter) {
+  for (int i0 = R.lo + threadIdx.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+    RowsE<N, Far, Unif> e;
+    e.load(V, i0, R.hi);
+    e.run(A, V, d, s, alpha, omega, iter);
+  }
 }
 
-template <int N, bool Far, bool Unif, bool Defer>
+template <int N, bool Far, bool Unif>
 __device__ __forceinline__ void std_E_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                            const Shm<N>& s, double alpha, double omega, int iter) {
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
   std_E_rows<N, Far, Unif>(A, V, R, d, s, alpha, omega, iter);
-  if constexpr (Defer) (void)block_publish<N, 2>(d, s, red, SLOT_RHO, rec);
-  else publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
+  publish_step<N, 2, FIN_BETA>(d, s, V, red, rec);
 }
 
 // true residual ||b - A x|| (reported at exit): partial <e, e> (slot 0)
@@ -884,24 +930,55 @@ __global__ void __launch_bounds__(1024) k_std_init(Csr A, Vecs V, Red red) {
 }
 
 // Single solves with exact or plain dots take the standard loop's reduction
-// points deferred (consume_step); lightweight dots keep the last-workgroup
+// points deferred (Deferred); lightweight dots keep the last-workgroup
 // finish, which merges the workgroups' FPE records once rather than in every
 // workgroup.
+// Row pairs of the first loop steps whose operands a deferred kernel loads while
+// the point it needs is fetched and rounded: as many as its registers take
+// without spilling (C: all four of a thread's pairs at two workgroups per CU on
+// 2M rows).
+template <bool Unif>
+constexpr int pf_a() {
+  return Unif ? 3 : 2;
+}
+constexpr int PF_C = 4, PF_E = 1;
+
 template <int N, bool Far, bool Unif>
 __global__ void __launch_bounds__(1024) k_std_A(Csr A, Vecs V, Red red) {
   if constexpr (defer_std<N>()) {
     extern __shared__ __align__(16) char smem[];
     Shm<N> s = shm_carve<N>(smem, 2, false);
+    const Range R = my_rows(A.n);
+    Deferred<N, 2> q;
+    q.issue(red, SLOT_RHO, V.st);
+    RowsA<Far, Unif> pf[pf_a<Unif>()];
+#pragma unroll
+    for (int k = 0; k < pf_a<Unif>(); ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].load(A, V, i, R.hi);
+    }
     if (blockIdx.x == 0) block_clear_slots<N, 2>(red, SLOT_THETA);
-    const int fl = wg_flags(s, V.st);
+    const int fl = q.flags(s);
     if (fl & 1) return;
     double beta = V.st->beta;
     bool upd = V.st->iter > 0;
     if (fl & 2) {  // S10, S11 and the stop test, on the dots E published
-      if (consume_step<N, 2, FIN_BETA>(s, V, red, SLOT_RHO, beta)) return;
+      if (q.template step<FIN_BETA>(s, V, red, SLOT_RHO, beta)) return;
       upd = true;
     }
-    std_A_body<Far, Unif>(A, V, my_rows(A.n), beta, V.st->omega, upd);
+    if constexpr (Unif)
+      if (!upd) return;  // p = r0 from the set-up
+    const double omega = V.st->omega;
+#pragma unroll
+    for (int k = 0; k < pf_a<Unif>(); ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].run(V, beta, omega, upd);
+    }
+    for (int i0 = R.lo + threadIdx.x + 2 * pf_a<Unif>() * blockDim.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+      RowsA<Far, Unif> a;
+      a.load(A, V, i0, R.hi);
+      a.run(V, beta, omega, upd);
+    }
   } else {
     const State* st = V.st;
     if (st->done) return;
@@ -933,10 +1010,28 @@ __global__ void __launch_bounds__(1024) k_std_C(Csr A, Vecs V, Red red) {
   if constexpr (defer_std<N>()) {
     extern __shared__ __align__(16) char smem[];
     Shm<N> s = shm_carve<N>(smem, 1, false);
-    if (wg_flags(s, V.st) & 1) return;
+    const Range R = my_rows(A.n);
+    Deferred<N, 1> q;
+    q.issue(red, SLOT_SIGMA, V.st);
+    RowsC<Far, Unif> pf[PF_C];
+#pragma unroll
+    for (int k = 0; k < PF_C; ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].load(A, V, i, R.hi);
+    }
+    if (q.flags(s) & 1) return;
     double alpha;
-    if (consume_step<N, 1, FIN_ALPHA>(s, V, red, SLOT_SIGMA, alpha)) return;  // S3
-    std_C_body<Far, Unif>(A, V, my_rows(A.n), alpha);
+    if (q.template step<FIN_ALPHA>(s, V, red, SLOT_SIGMA, alpha)) return;  // S3
+#pragma unroll
+    for (int k = 0; k < PF_C; ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].run(V, alpha);
+    }
+    for (int i0 = R.lo + threadIdx.x + 2 * PF_C * blockDim.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+      RowsC<Far, Unif> c;
+      c.load(A, V, i0, R.hi);
+      c.run(V, alpha);
+    }
   } else {
     if (V.st->done) return;
     std_C_body<Far, Unif>(A, V, my_rows(A.n), V.st->alpha);
@@ -959,17 +1054,41 @@ __global__ void __launch_bounds__(1024) k_std_E(Csr A, Vecs V, Red red) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   if constexpr (defer_std<N>()) {
-    if (wg_flags(s, V.st) & 1) return;
+    const Range R = my_rows(A.n);
+    Deferred<N, 2> q;
+    q.issue(red, SLOT_THETA, V.st);
+    RowsE<N, Far, Unif> pf[PF_E];
+#pragma unroll
+    for (int k = 0; k < PF_E; ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].load(V, i, R.hi);
+    }
+    if (q.flags(s) & 1) return;
     double omega;
-    if (consume_step<N, 2, FIN_OMEGA>(s, V, red, SLOT_THETA, omega)) return;  // S7
+    if (q.template step<FIN_OMEGA>(s, V, red, SLOT_THETA, omega)) return;  // S7
     shm_init(s, 2);
-    std_E_body<N, Far, Unif, true>(A, V, red, my_rows(A.n), blockIdx.x, s, V.st->alpha, omega, V.st->iter);
+    const double alpha = V.st->alpha;
+    const int iter = V.st->iter;
+    Dot<N> d[2];
+    d[0].zero();
+    d[1].zero();
+#pragma unroll
+    for (int k = 0; k < PF_E; ++k) {
+      const int i = R.lo + threadIdx.x + 2 * k * blockDim.x;
+      if (i < R.hi) pf[k].run(A, V, d, s, alpha, omega, iter);
+    }
+    for (int i0 = R.lo + threadIdx.x + 2 * PF_E * blockDim.x; i0 < R.hi; i0 += 2 * blockDim.x) {
+      RowsE<N, Far, Unif> e;
+      e.load(V, i0, R.hi);
+      e.run(A, V, d, s, alpha, omega, iter);
+    }
+    (void)block_publish<N, 2>(d, s, red, SLOT_RHO, blockIdx.x);
     if (threadIdx.x == 0) V.st->pend = 1;
   } else {
     const State* st = V.st;
     if (st->done) return;
     shm_init(s, 2);
-    std_E_body<N, Far, Unif, false>(A, V, red, my_rows(A.n), blockIdx.x, s, st->alpha, st->omega, st->iter);
+    std_E_body<N, Far, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s, st->alpha, st->omega, st->iter);
   }
 }
 
