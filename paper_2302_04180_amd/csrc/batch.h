@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) kb_setup(Batch B, double tol, int maxit, 
       st->varsigma = 0.0; st->zeta = 0.0;
       st->iter = 0; st->maxit = maxit; st->done = 0; st->status = 0;
       st->variant = variant; st->resumable = 0; st->lost = 0; st->spmv_go = 0;
-      st->rho_n = 0.0; st->pend = 0; st->iter_n = 0;
+      st->stg = 0.0; st->pend = 0; st->iter_n = 0;
     }
   }
 }
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(1024) kb_pcg_S1(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   tile_loop<N, 1, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pcg_S1_body<N>(D.A, D.V, D.red, R, rec, s);
+    pcg_S1_body<N, false>(D.A, D.V, D.red, R, rec, s);
   });
 }
 
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(1024) kb_pcg_S3(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
   tile_loop<N, 2, true>(B, s, blockIdx.x, gridDim.x, [&](const SysDesc& D, Range R, int rec) {
-    pcg_S3_body<N, Unif>(D.A, D.V, D.red, R, rec, s);
+    pcg_S3_body<N, Unif, false>(D.A, D.V, D.red, R, rec, s, D.V.st->rho, D.V.st->iter);
   });
 }
 
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(1024) kb_pcg_S10(Batch B) {
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 0, false);
   tile_loop<N, 0, true>(B, s, blockIdx.x, gridDim.x,
-                        [&](const SysDesc& D, Range R, int) { pcg_S10_body<Unif>(D.A, D.V, R); });
+                        [&](const SysDesc& D, Range R, int) { pcg_S10_body<Unif>(D.A, D.V, R, D.V.st->alpha); });
 }
 
 // Third set-up step of the pipelined loop over all tiles: t = A w^ (the loop's

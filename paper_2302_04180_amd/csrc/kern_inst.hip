@@ -75,14 +75,16 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
                    : launch(k_std_E<N, false, false>, G, B, s2e, s, A, V, red);
     }
   }
-  if (variant == RPK_PCG) {
+  if (variant == RPK_PCG) {  // S10 (finishing the iteration before), S1, S3
+    const size_t s2e = shm_bytes(N, 2, false, B);
     switch (ph) {
-      case 0: return launch(k_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
-      case 1:
-        return A.unif ? launch(k_pcg_S3<N, true>, G, B, shm_bytes(N, 2, false, B), s, A, V, red)
-                      : launch(k_pcg_S3<N, false>, G, B, shm_bytes(N, 2, false, B), s, A, V, red);
+      case 0:
+        return A.unif ? launch(k_pcg_S10<N, true>, G, B, s2e, s, A, V, red)
+                      : launch(k_pcg_S10<N, false>, G, B, s2e, s, A, V, red);
+      case 1: return launch(k_pcg_S1<N>, G, B, shm_bytes(N, 1, true, B), s, A, V, red);
       default:
-        return A.unif ? launch(k_pcg_S10<N, true>, G, B, 0, s, A, V) : launch(k_pcg_S10<N, false>, G, B, 0, s, A, V);
+        return A.unif ? launch(k_pcg_S3<N, true>, G, B, s2e, s, A, V, red)
+                      : launch(k_pcg_S3<N, false>, G, B, s2e, s, A, V, red);
     }
   }
   // the SpMVs carry one more workgroup (the finisher of the reduction before them)

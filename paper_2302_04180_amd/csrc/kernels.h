@@ -72,13 +72,13 @@ struct Csr {
 struct State {
   double alpha, omega, beta, rho, tau, tau0, tol, true_res;
   double varsigma, zeta;  // pipelined: <r0,s>, <r0,z> of the current iteration (S16, taken in P1)
-  double rho_n;           // standard loop, deferred reductions: rho after S10, moved to rho by B
+  double stg;             // deferred reductions: rho after S10 (standard) / beta after S6 (PCG), moved by B / S1
   int iter, maxit, done, status;
   int variant, resumable;
   int lost;     // lightweight mode: dot products that could not keep every bit
   int spmv_go;  // pipelined: 1 when the kernel before an SpMV ran (written by that kernel only)
-  int pend;     // standard loop, deferred reductions: E published S10/S11 and A has not taken them
-  int iter_n;   // standard loop, deferred reductions: iter after S10, moved to iter by B
+  int pend;     // deferred reductions: E (PCG: S3) published its dots, A (S10) has not taken them
+  int iter_n;   // deferred reductions: iter after the stop test, moved to iter by B (PCG: S1)
 };
 
 // Reduction scratch in the caller's workspace (left zeroed after every use).

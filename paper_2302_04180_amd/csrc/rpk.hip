@@ -579,11 +579,6 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
     }
     if (hipMemcpyAsync(g_pinned, V.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RPK_ERR_HIP; break; }
-    // PCG: a solve stopped at its limit after S9 still owes S10 (p := y + alpha p),
-    // which opens the next iteration; a resumed solve takes it once here.
-    if (resume && variant == RPK_PCG && !g_pinned->done && g_pinned->iter > 0)
-      st = by_dot<PhaseF>(N, variant, 2, G, B, s, Ac, V, red);
-    if (st != RPK_OK) break;
     const bool use_graph = !timing && c.graph >= 0;
     int chunk = c.graph > 0 ? c.graph : 4;
     long long launched = 0;
@@ -637,6 +632,12 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
       if (c.graph == 0 && chunk < 32) chunk *= 2;
     }
     if (st != RPK_OK) break;
+    // reduction slots that a stop left published but not cleared (the kernels
+    // that clear them did not run), so that the residual and a resumed solve
+    // start from zeroed accumulators
+    hipLaunchKernelGGL(k_zero_words, dim3(16), dim3(256), 0, s, (unsigned*)(w + l.tickets),
+                       (long long)((l.partials - l.tickets) / sizeof(unsigned)));
+    if (hipGetLastError() != hipSuccess) { st = RPK_ERR_HIP; break; }
     // true residual of the returned iterate, exact
     if (timing && hipEventRecord(ev[0], s) != hipSuccess) { st = RPK_ERR_HIP; break; }
     st = Kern<4>::resid(G, B, s, Ac, V, red);

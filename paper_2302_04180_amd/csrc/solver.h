@@ -76,7 +76,7 @@ __device__ __forceinline__ void state_load(State& d, const State* s) {
   d.varsigma = s->varsigma; d.zeta = s->zeta;
   d.iter = s->iter; d.maxit = s->maxit; d.done = s->done; d.status = s->status;
   d.variant = s->variant; d.resumable = s->resumable; d.lost = s->lost; d.spmv_go = 0;
-  d.rho_n = 0.0; d.pend = 0; d.iter_n = 0;
+  d.stg = 0.0; d.pend = 0; d.iter_n = 0;
 }
 
 __device__ __forceinline__ void state_store(State* d, const State& s) {
@@ -336,12 +336,17 @@ __device__ __forceinline__ void publish_or_defer(Dot<N> (&d)[K], const Shm<N>& s
 // rounding at the start of that kernel instead of two device-wide round trips
 // and a serial rounding at the end of the kernel before it.  All copies compute the same
 // bits.  Workgroup 0 stores what the step decided, only into fields that no
-// workgroup of the same kernel reads: S10/S11 leave iter and rho in iter_n and
-// rho_n, which B moves.  The slots are cleared two kernels after their
-// publication: D clears B's, A clears D's, B clears E's.
+// workgroup of the same kernel reads: the stop test leaves iter and rho (PCG:
+// beta) in iter_n and stg, which the next kernel, B (PCG: S1), moves.  The slots
+// are cleared two kernels after their publication: D clears B's, A clears D's,
+// B clears E's (PCG: S10 clears S1's, S1 clears S3's), and the host clears them
+// all when the loop ends.  PCG runs S10 first in each iteration (it finishes
+// the iteration before, from the state, in the first one nothing).
 constexpr int SLOT_SIGMA = 0;  // B: <r0,s>
 constexpr int SLOT_THETA = 1;  // D: <q,y>, <y,y>
 constexpr int SLOT_RHO = 3;    // E: <r0,r>, <r,r>
+constexpr int SLOT_PD = 0;     // PCG S1: <p,d>
+constexpr int SLOT_YR = 1;     // PCG S3: <y,r>, <r,r>
 
 template <int N>
 constexpr bool defer_std() {
@@ -353,7 +358,8 @@ constexpr bool defer_std() {
 // thread 0, the state) so that the caller can issue its own first loads behind
 // them; flags() returns done | pend << 1 of the state as loaded, the same in
 // every thread; step<F>() rounds the dots and takes step F (S3: alpha, S7: omega,
-// S10/S11: tau, stop test, beta) on the loaded state, and returns, in every
+// S10/S11: tau, stop test, beta; PCG S2: rho, S6..S9: beta, tau, stop test,
+// alpha) on the loaded state, and returns, in every
 // thread, whether the step stopped the solve, with the step's scalar in `out`.
 // The state may change under the kernel only in fields the step does not read,
 // or in done, which the step would set the same way.
@@ -391,15 +397,29 @@ struct Deferred {
         step_omega(&S, h, s.res[0], s.res[1], 2);
         s.res[MAX_DOTS - 1] = S.omega;
         if (w0) st->omega = S.omega;
-      } else {
-        static_assert(F == FIN_BETA, "deferred points: S3, S7, S10/S11");
+      } else if constexpr (F == FIN_BETA) {
         step_std_beta(&S, h, s.res[0], s.res[1]);
         s.res[MAX_DOTS - 1] = S.beta;
         if (w0) {
           st->beta = S.beta;
           st->tau = S.tau;
           st->resumable = S.resumable;
-          st->rho_n = S.rho;
+          st->stg = S.rho;
+          st->iter_n = S.iter;
+        }
+      } else if constexpr (F == FIN_PCG_RHO) {
+        step_pcg_rho(&S, h, s.res[0]);
+        s.res[MAX_DOTS - 1] = S.rho;
+        if (w0) st->rho = S.rho;
+      } else {
+        static_assert(F == FIN_PCG_BETA, "deferred points: S3, S7, S10/S11; PCG S2, S6..S9");
+        step_pcg_beta(&S, h, s.res[0], s.res[1]);
+        s.res[MAX_DOTS - 1] = S.alpha;
+        if (w0) {
+          st->alpha = S.alpha;
+          st->tau = S.tau;
+          st->resumable = S.resumable;
+          st->stg = S.beta;
           st->iter_n = S.iter;
         }
       }
@@ -863,7 +883,7 @@ __device__ __forceinline__ void pcg_init_body(const Csr& A, const Vecs& V, const
 }
 
 // S1 d = A p + partial <p,d> (S2)
-template <int N>
+template <int N, bool Defer>
 __device__ __forceinline__ void pcg_S1_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
                                             const Shm<N>& s) {
   Dot<N> d[1];
@@ -878,37 +898,56 @@ __device__ __forceinline__ void pcg_S1_body(const Csr& A, const Vecs& V, const R
       d[0].add(pi, di, s.sa, &s.flag[0]);
     }
   }
-  publish_step<N, 1, FIN_PCG_RHO>(d, s, V, red, rec);
+  if constexpr (Defer) (void)block_publish<N, 1>(d, s, red, SLOT_PD, rec);
+  else publish_step<N, 1, FIN_PCG_RHO>(d, s, V, red, rec);
 }
 
-// S3 x = fma(rho, p, x), S4 r = fma(-rho, d, r), S5 y = M^-1 r ; partials <y,r>, <r,r> (S7, S8)
-template <int N, bool Unif>
+// S3 x = fma(rho, p, x), S4 r = fma(-rho, d, r), S5 y = M^-1 r ; partials <y,r>,
+// <r,r> (S7, S8), on row i
+template <bool Unif>
+struct RowsP3 {
+  double p, x, d, r, dv;
+  __device__ __forceinline__ void load(const Csr& A, const Vecs& V, int i) {
+    p = V.p[i];
+    x = V.x[i];
+    d = V.s[i];
+    r = V.r[i];
+    if constexpr (!Unif) dv = A.dinv[i];
+  }
+  template <int N>
+  __device__ __forceinline__ void run(const Csr& A, const Vecs& V, int i, double rho, int iter, Dot<N> (&dd)[2],
+                                      const Shm<N>& s) const {
+    const double xn = fma(rho, p, x);   // S3
+    const double rn = fma(-rho, d, r);  // S4
+    const double y = (Unif ? A.du : dv) * rn;  // S5
+    V.x[i] = xn;
+    V.r[i] = rn;
+    if constexpr (!Unif) V.y[i] = y;
+    record_xr(V, iter, A.n, i, xn, rn);
+    dd[0].add(y, rn, s.sa, &s.flag[0]);         // S7
+    dd[1].add(rn, rn, s.sa + SA_D, &s.flag[1]);  // S8
+  }
+};
+
+template <int N, bool Unif, bool Defer>
 __device__ __forceinline__ void pcg_S3_body(const Csr& A, const Vecs& V, const Red& red, Range R, int rec,
-                                            const Shm<N>& s) {
-  const State* st = V.st;
-  const double rho = st->rho;
-  const int iter = st->iter;
+                                            const Shm<N>& s, double rho, int iter) {
   Dot<N> d[2];
   d[0].zero();
   d[1].zero();
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x) {
-    const double x = fma(rho, V.p[i], V.x[i]);    // S3
-    const double r = fma(-rho, V.s[i], V.r[i]);   // S4
-    const double y = (Unif ? A.du : A.dinv[i]) * r;  // S5
-    V.x[i] = x;
-    V.r[i] = r;
-    if constexpr (!Unif) V.y[i] = y;
-    record_xr(V, iter, A.n, i, x, r);
-    d[0].add(y, r, s.sa, &s.flag[0]);             // S7
-    d[1].add(r, r, s.sa + SA_D, &s.flag[1]);      // S8
+    RowsP3<Unif> t;
+    t.load(A, V, i);
+    t.run(A, V, i, rho, iter, d, s);
   }
-  publish_step<N, 2, FIN_PCG_BETA>(d, s, V, red, rec);
+  if constexpr (Defer) (void)block_publish<N, 2>(d, s, red, SLOT_YR, rec);
+  else publish_step<N, 2, FIN_PCG_BETA>(d, s, V, red, rec);
 }
 
 // S10 p = fma(alpha, p, y)
 template <bool Unif>
-__device__ __forceinline__ void pcg_S10_body(const Csr& A, const Vecs& V, Range R) {
-  const double alpha = V.st->alpha, du = A.du;
+__device__ __forceinline__ void pcg_S10_body(const Csr& A, const Vecs& V, Range R, double alpha) {
+  const double du = A.du;
   for (int i = R.lo + threadIdx.x; i < R.hi; i += blockDim.x)
     V.p[i] = fma(alpha, V.p[i], Unif ? du * V.r[i] : V.y[i]);
 }
@@ -993,7 +1032,7 @@ __global__ void __launch_bounds__(1024) k_std_B(Csr A, Vecs V, Red red) {
       block_clear_slots<N, 2>(red, SLOT_RHO);
       if (threadIdx.x == 0 && V.st->pend) {
         V.st->iter = V.st->iter_n;
-        V.st->rho = V.st->rho_n;
+        V.st->rho = V.st->stg;
         V.st->pend = 0;
       }
     }
@@ -1184,31 +1223,113 @@ __global__ void __launch_bounds__(1024) k_pcg_init(Csr A, Vecs V, Red red) {
   pcg_init_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
+// PCG, one iteration = S10 (finishing the iteration before; nothing in the
+// first), S1, S3.  With exact or plain dots the points are deferred as in the
+// standard loop: S3 takes S2 (rho) from the dot S1 published, S10 takes S6..S9
+// from the dots S3 published.
+template <int N, bool Unif>
+__global__ void __launch_bounds__(1024) k_pcg_S10(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>()) {
+    extern __shared__ __align__(16) char smem[];
+    Shm<N> s = shm_carve<N>(smem, 2, false);
+    const Range R = my_rows(A.n);
+    Deferred<N, 2> q;
+    q.issue(red, SLOT_YR, V.st);
+    constexpr int PF = 8;  // a thread's rows at two workgroups per CU on 2M rows
+    double pp[PF], py[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = R.lo + threadIdx.x + k * blockDim.x;
+      if (i < R.hi) {
+        pp[k] = V.p[i];
+        py[k] = Unif ? V.r[i] : V.y[i];
+      }
+    }
+    if (blockIdx.x == 0) block_clear_slots<N, 1>(red, SLOT_PD);
+    const int fl = q.flags(s);
+    if (fl & 1) return;
+    double alpha = V.st->alpha;
+    bool has = V.st->iter > 0;
+    if (fl & 2) {  // S6..S9 on the dots S3 published
+      if (q.template step<FIN_PCG_BETA>(s, V, red, SLOT_YR, alpha)) return;
+      has = true;
+    }
+    if (!has) return;
+    const double du = A.du;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = R.lo + threadIdx.x + k * blockDim.x;
+      if (i < R.hi) V.p[i] = fma(alpha, pp[k], Unif ? du * py[k] : py[k]);  // S10
+    }
+    const Range Rt{R.lo + PF * (int)blockDim.x, R.hi};
+    if (Rt.lo < Rt.hi) pcg_S10_body<Unif>(A, V, Rt, alpha);
+  } else {
+    const State* st = V.st;
+    if (st->done || st->iter == 0) return;
+    pcg_S10_body<Unif>(A, V, my_rows(A.n), st->alpha);
+  }
+}
+
 template <int N>
 __global__ void __launch_bounds__(1024) k_pcg_S1(Csr A, Vecs V, Red red) {
+  if constexpr (defer_std<N>()) {
+    if (blockIdx.x == 0) {  // S10 has taken S3's dots: clear them, move iter and beta
+      block_clear_slots<N, 2>(red, SLOT_YR);
+      if (threadIdx.x == 0 && V.st->pend) {
+        V.st->iter = V.st->iter_n;
+        V.st->beta = V.st->stg;
+        V.st->pend = 0;
+      }
+    }
+  }
   if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 1, true);
   shm_init(s, 1);
-  pcg_S1_body<N>(A, V, red, my_rows(A.n), blockIdx.x, s);
+  pcg_S1_body<N, defer_std<N>()>(A, V, red, my_rows(A.n), blockIdx.x, s);
 }
 
 template <int N, bool Unif>
 __global__ void __launch_bounds__(1024) k_pcg_S3(Csr A, Vecs V, Red red) {
-  if (V.st->done) return;
   extern __shared__ __align__(16) char smem[];
   Shm<N> s = shm_carve<N>(smem, 2, false);
-  shm_init(s, 2);
-  pcg_S3_body<N, Unif>(A, V, red, my_rows(A.n), blockIdx.x, s);
-}
-
-// S10 opens the next iteration: after a stop at the iteration limit it is left
-// to the resumed solve (it is not idempotent, and the kernels of the iterations
-// still queued behind the stop see the same state).
-template <int N, bool Unif>
-__global__ void __launch_bounds__(1024) k_pcg_S10(Csr A, Vecs V) {
-  if (V.st->done) return;
-  pcg_S10_body<Unif>(A, V, my_rows(A.n));
+  if constexpr (defer_std<N>()) {
+    const Range R = my_rows(A.n);
+    Deferred<N, 1> q;
+    q.issue(red, SLOT_PD, V.st);
+    constexpr int PF = 4;
+    RowsP3<Unif> pf[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = R.lo + threadIdx.x + k * blockDim.x;
+      if (i < R.hi) pf[k].load(A, V, i);
+    }
+    if (q.flags(s) & 1) return;
+    double rho;
+    if (q.template step<FIN_PCG_RHO>(s, V, red, SLOT_PD, rho)) return;  // S2
+    shm_init(s, 2);
+    const int iter = V.st->iter;
+    Dot<N> d[2];
+    d[0].zero();
+    d[1].zero();
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = R.lo + threadIdx.x + k * blockDim.x;
+      if (i < R.hi) pf[k].run(A, V, i, rho, iter, d, s);
+    }
+    for (int i = R.lo + threadIdx.x + PF * blockDim.x; i < R.hi; i += blockDim.x) {
+      RowsP3<Unif> t;
+      t.load(A, V, i);
+      t.run(A, V, i, rho, iter, d, s);
+    }
+    (void)block_publish<N, 2>(d, s, red, SLOT_YR, blockIdx.x);
+    if (threadIdx.x == 0) V.st->pend = 1;
+  } else {
+    const State* st = V.st;
+    if (st->done) return;
+    shm_init(s, 2);
+    pcg_S3_body<N, Unif, false>(A, V, red, my_rows(A.n), blockIdx.x, s, st->rho, st->iter);
+  }
 }
 
 }  // namespace rpk
