@@ -42,7 +42,7 @@ MAXIT = 5000
 # had when the profiles were taken and the solve runs the same FPE length.
 TRAFFIC = {"phase": 3, "kernel": "k_std_D<3, true>", "fpe": 3, "bytes": 212945350,
            "fetch_scale": 1.9999, "write_scale": 1.0000, "trace_busy_avg_us": 49.4,
-           "src_sha256": "facab4d2b15d1fe4774848691e699e228ea9e7f1821b9b17210a5d4770e9d21e"}
+           "src_sha256": "09a4cf6a2055e4e20fd6e527d19f4a483f6fe768d6642d6577143657850f557f"}
 
 
 KERNEL_SOURCES = ("device.h", "kernels.h", "solver.h")
@@ -604,8 +604,8 @@ def main():
 
     # per-kernel times of one instrumented exact solve (HIP events on the solve's stream)
     tinfo = solve(timing=True)
-    names = ["A: S12+S1", "B: S2 SpMV + S3 -> alpha", "C: S4+S5", "D: S6 SpMV + S7 -> omega",
-             "E: S8+S9 + S10/S11 -> tau, beta"]
+    names = ["A: S12+S1", "B: S2 SpMV + S3 dot", "C: S4+S5", "D: S6 SpMV + S7 dots",
+             "E: S8+S9 + S10/S11 dots"]
     phase = {}
     for k, nm in enumerate(names):
         if tinfo["phase_launches"][k]:

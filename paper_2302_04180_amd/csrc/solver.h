@@ -1,9 +1,11 @@
 // solver.h -- fused phase kernels of PBiCGStab (Fig. 2) and p-PBiCGStab (Fig. 3).
 //
-// Standard loop, five kernels per iteration.  Each reduction point ends a
-// kernel: the last workgroup to finish rounds the dot products and takes the
-// scalar step (kernels.h, block_publish_last), so no separate finishing kernel
-// and no grid-wide fence is needed.  Recomputing p^ / q^ inside the SpMV
+// Standard loop, five kernels per iteration.  Each reduction point's terms end
+// a kernel, which publishes them; with exact or plain dots every workgroup of
+// the next kernel rounds them and takes the scalar step (Deferred), with
+// lightweight dots (and in the batched loop) the last workgroup of the
+// publishing kernel does (kernels.h, block_publish_last), so no separate
+// finishing kernel and no grid-wide fence is needed.  Recomputing p^ / q^ inside the SpMV
 // gathers instead of storing them was measured slower: it multiplies the
 // gathered vectors by 3-4 (gathering p and dinv alone, 2, still cost more than
 // the stores it saves).  Where the Jacobi vector is uniform (Csr::unif) they are
@@ -11,11 +13,15 @@
 // stored: 19 vector streams per iteration instead of 25.  The host picks that
 // path (the Unif instantiations) per launch: for a single solve from the
 // matrix, for a batch when every system's Jacobi vector is uniform.
-//   A: S12 (from the second iteration on) + S1
-//   B: S2 SpMV (gathers p^) + S3                  -> last workgroup: alpha
-//   C: S4 + S5
-//   D: S6 SpMV (gathers q^) + S7                  -> last workgroup: omega
-//   E: S8 + S9, S10/S11                           -> last workgroup: tau, stop test, beta
+//   A: [tau, stop test, beta] S12 (from the second iteration on) + S1
+//   B: S2 SpMV (gathers p^) + <r0,s> of S3        -> published
+//   C: [alpha] S4 + S5
+//   D: S6 SpMV (gathers q^) + <q,y>, <y,y> of S7  -> published
+//   E: [omega] S8 + S9, <r0,r>, <r,r> of S10/S11  -> published
+// ([..]: the deferred scalar step, taken at the kernel's start; with
+// lightweight dots the last workgroup of B, D, E takes alpha, omega, beta.)
+// PCG, three kernels per iteration: S10 [beta, tau, stop test, alpha of the
+// iteration before], S1 SpMV + <p,d>, S3 [rho] + S4, S5 + <y,r>, <r,r>.
 // Pipelined loop, four kernels per iteration.  Each reduction of Fig. 3 is
 // published by the kernel that produces its terms and finished by workgroup 0
 // of the SpMV kernel after it, while that kernel's other workgroups compute the
