@@ -542,19 +542,6 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Block-wide max of v (all threads get it).  Uses s.imax; ends with a barrier.
-template <int N>
-__device__ __forceinline__ int block_max_int(int v, const Shm<N>& s) {
-  v = wave_max_int(v);
-  const int nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) s.imax[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int m = s.imax[0];
-  for (int i = 1; i < nw; ++i) m = (s.imax[i] > m) ? s.imax[i] : m;
-  __syncthreads();
-  return m;
-}
-
 // Block-wide max of K values per thread (all threads get them).  Uses s.imax; ends with a barrier.
 template <int N, int K>
 __device__ __forceinline__ void block_max_k(int (&v)[K], const Shm<N>& s) {

@@ -277,3 +277,40 @@ def test_uniform_and_nonuniform_jacobi_paths(orc, variant, vname):
         k = ro["iters"]
         assert same(H(ig["xr"])[:k], ro["xr"][:k])
         M.close()
+
+
+# Workspace header of a single solve: device state (256 bytes) | arrival counters and
+# non-finite flags (256) | 8 global long accumulators of 136 int64 digits | per-
+# workgroup partial records.  The reduction points of the standard loop and PCG are
+# read by the kernel after the one that published them and cleared two kernels
+# later, and by the host when the loop ends; a resumed solve, or the next solve on
+# the same workspace, relies on finding counters, flags and digits at zero.
+_RED_LO, _RED_HI = 256, 256 + 256 + 8 * 136 * 8
+
+
+@pytest.mark.parametrize("variant", [rpk.STD, rpk.PCG, rpk.PIPELINED], ids=["std", "pcg", "pipelined"])
+@pytest.mark.parametrize("dots", [rpk.EXACT, rpk.PLAIN, rpk.FPE], ids=["exact", "plain", "fpe"])
+def test_reduction_slots_left_zeroed(orc, variant, dots):
+    import torch
+    A = inputs.poisson7(12)
+    M = rpk.Matrix(*A)
+    b = rhs(orc, M, A, inputs.uniform(12 ** 3, 5))
+    nb = rpk.solve_workspace_bytes(M, variant, dots=dots)
+    ws = torch.full((nb,), 0xA5, dtype=torch.uint8, device="cuda")
+    for maxit, want in ((3, "NOT_CONVERGED"), (500, "OK")):
+        x, info = rpk.solve(M, T(b), tol=1e-10, maxit=maxit, variant=variant, dots=dots, workspace=ws)
+        red = H(ws[_RED_LO:_RED_HI])
+        say(variant, dots, "maxit", maxit, info["status"], info["iters"], "non-zero bytes", int(np.count_nonzero(red)))
+        assert info["status"] == want
+        assert not red.any(), np.flatnonzero(red)[:16]
+    # a breakdown at the first reduction point (<r0, A M^-1 r0> = 0)
+    rp = np.array([0, 2, 3], np.int32)
+    ci = np.array([0, 1, 1], np.int32)
+    v = np.array([1.0, 2.0, -1.0])
+    M2 = rpk.Matrix(rp, ci, v)
+    if variant != rpk.PCG:  # PCG needs a symmetric positive definite matrix
+        nb2 = rpk.solve_workspace_bytes(M2, variant, dots=dots)
+        ws2 = torch.zeros(nb2, dtype=torch.uint8, device="cuda")
+        x, info = rpk.solve(M2, T([1.0, 1.0]), tol=1e-12, maxit=10, variant=variant, dots=dots, workspace=ws2)
+        assert info["status"] == "BREAKDOWN"
+        assert not H(ws2[_RED_LO:_RED_HI]).any()
