@@ -333,21 +333,21 @@ __device__ __forceinline__ void publish_or_defer(Dot<N> (&d)[K], const Shm<N>& s
   else publish_step<N, K, F>(d, s, V, red, rec);
 }
 
-// Deferred reduction points of the standard loop (single solves, exact and
-// plain dots).  The kernel that produces a point's terms only publishes them,
-// with neither an arrival count nor a last workgroup; every workgroup of the
-// kernel that needs the result rounds the dots itself from the published
+// Deferred reduction points of the standard loop and PCG (single solves, exact
+// and plain dots).  The kernel that produces a point's terms only publishes
+// them, with neither an arrival count nor a last workgroup; every workgroup of
+// the kernel that needs the result rounds the dots itself from the published
 // accumulators (read, not cleared) and takes the scalar step on its own copy of
-// the state, while its first operands load, so a reduction point costs a
+// the state while its first operands load, so a reduction point costs a
 // rounding at the start of that kernel instead of two device-wide round trips
-// and a serial rounding at the end of the kernel before it.  All copies compute the same
-// bits.  Workgroup 0 stores what the step decided, only into fields that no
-// workgroup of the same kernel reads: the stop test leaves iter and rho (PCG:
-// beta) in iter_n and stg, which the next kernel, B (PCG: S1), moves.  The slots
-// are cleared two kernels after their publication: D clears B's, A clears D's,
-// B clears E's (PCG: S10 clears S1's, S1 clears S3's), and the host clears them
-// all when the loop ends.  PCG runs S10 first in each iteration (it finishes
-// the iteration before, from the state, in the first one nothing).
+// and a serial rounding at the end of the kernel before it.  All copies compute
+// the same bits.  Workgroup 0 stores what the step decided, only into fields
+// that no workgroup of the same kernel reads: the stop test leaves iter and rho
+// (PCG: beta) in iter_n and stg, which the next kernel, B (PCG: S1), moves.  The
+// slots are cleared two kernels after their publication: D clears B's, A clears
+// D's, B clears E's (PCG: S10 clears S1's, S1 clears S3's), and the host clears
+// them all when the loop ends.  PCG runs S10 first in each iteration: it
+// finishes the iteration before (in the first iteration it does nothing).
 constexpr int SLOT_SIGMA = 0;  // B: <r0,s>
 constexpr int SLOT_THETA = 1;  // D: <q,y>, <y,y>
 constexpr int SLOT_RHO = 3;    // E: <r0,r>, <r,r>
