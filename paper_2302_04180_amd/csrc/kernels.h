@@ -21,8 +21,9 @@ namespace rpk {
 constexpr int HIST_W = 12;   // doubles per recorded iteration
 constexpr int MAX_DOTS = 8;  // reduction slots in the workspace
 // Exact cross-lane reduction: each workgroup sums its lanes' FPE components as
-// integers in a window of WIN digits of the long-accumulator grid, anchored at
-// the workgroup's leading digit, and adds the window into the dot's global long
+// integers in a window of WIN digits of the long-accumulator grid, whose top is
+// the highest digit the workgroup's largest component reaches, and adds the
+// window into the dot's global long
 // accumulator.  Digits that fall below the window (components more than about
 // 290 bits below the workgroup's largest) go to the long accumulator directly,
 // so nothing is ever dropped.

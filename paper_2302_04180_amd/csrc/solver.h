@@ -249,7 +249,7 @@ __device__ __forceinline__ void step_pipe_s19(State* st, double* h, const double
   if (at_max) stop_at_maxit(st, false);
 }
 
-// Reduction points: which scalar step the last workgroup takes.
+// Reduction points: which scalar step the workgroup that finishes a point takes.
 enum : int {
   FIN_ENTRY = 0,     // <r0,r0>            -> tau0, loop entry test (standard)
   FIN_ALPHA = 1,     // <r0,s>             -> alpha (S3)
