@@ -337,26 +337,40 @@ __device__ __forceinline__ double row_fast(const double* __restrict__ sval, cons
   return ovf ? 0.0 : fpe_round(f);
 }
 
+// twosum as a value (r = RN(x + y)) and its exact error in `err`
+__device__ __forceinline__ double tsum(double x, double y, double& err) {
+  const double r = x + y;
+  const double z = r - x;
+  err = (x - (r - z)) + (y - z);
+  return r;
+}
+
 // Certified fast path of one row in one lane: the compensated dot product of
-// Ogita, Rump and Oishi (2005, Dot2) with its error bound.  With p_j + e_j =
-// a_j x_j (twoprod, exact for products in range) and t_j the errors of the
-// running sum s (twosum, exact), the row sum is exactly T = s + sum(t_j + e_j);
-// q = fl(sum(t_j + e_j)) is within E = gamma_k * sum(|t_j| + |e_j|) (k > 2w terms,
-// plus an allowance for underflow) of that sum.  With (y, r) = twosum(s, q),
-// T = y + r + d with |d| <= E, so y = RN(T) whenever |r| + E is below half the
-// gap from y to its neighbours.  Track: also check with twosum that every
-// addition into q was exact; then T = s + q and y = RN(s + q) is RN(T) even
-// when T is a rounding midpoint, which no bound can settle (sums of a few
-// exact products often are).  Returns false -- the caller then takes the FPE
-// path -- when neither shows it, or for a product out of range or a sum that
-// is non-finite or, for the bound, zero, tiny or huge.  When it returns true, y
-// is the correctly rounded row sum: the same bits as the FPE path.
+// Ogita, Rump and Oishi (2005, Dot2) with its error bound, summed pairwise.
+// With p_j + e_j = a_j x_j (twoprod, exact for products in range), each batch
+// of eight products is added by a tree of twosums (exact) and the batch sum
+// into the running sum s by one more; with t the errors of those eight
+// additions, the row sum is exactly T = s + sum(t + e), sixteen terms per
+// batch.  q = fl(sum(t + e)), also summed pairwise, is within
+// E = gamma_k * sum(|t| + |e|) of that sum for any order of the additions
+// (k at least the number of terms, plus an allowance for underflow).  With
+// (y, r) = twosum(s, q), T = y + r + d with |d| <= E, so y = RN(T) whenever
+// |r| + E is below half the gap from y to its neighbours.  Track: also check
+// with twosum that every addition into q was exact; then T = s + q and
+// y = RN(s + q) is RN(T) even when T is a rounding midpoint, which no bound can
+// settle (sums of a few exact products often are).  Returns false -- the
+// caller then takes the FPE path -- when neither shows it, or for a product
+// out of range or a sum that is non-finite or, for the bound, zero, tiny or
+// huge.  When it returns true, y is the correctly rounded row sum: the same
+// bits as the FPE path.  The trees keep the dependent chains of a batch at
+// three and four additions instead of eight and sixteen.
 template <bool Track, bool NT, class Gth>
 __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const int* __restrict__ scol, const Gth& gx,
                                          int w, double& y) {
   double s = 0.0, q = 0.0, m = 0.0;
   bool ok = true, exactq = true;
-  for (int j0 = 0; j0 < w; j0 += 8) {
+  int nb = 0;  // batches of eight entries
+  for (int j0 = 0; j0 < w; j0 += 8, ++nb) {
     double a[8], b[8];
     int c[8];
 #pragma unroll
@@ -369,37 +383,55 @@ __device__ __forceinline__ bool row_cert(const double* __restrict__ sval, const 
     for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.load(c[u]) : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) b[u] = (c[u] >= 0) ? gx.fin(b[u]) : 0.0;
+    // v[0..7]: the errors t of the batch's additions, v[8..15]: the products' e
+    double p[8], v[16];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const double p = a[u] * b[u];
-      const double ap = fabs(p);
-      ok &= (ap >= kProdLo && ap < kProdHi) || (p == 0.0 && (a[u] == 0.0 || b[u] == 0.0));
-      const double e = fma(a[u], b[u], -p);
-      const double s1 = s + p;
-      const double z = s1 - s;
-      const double t = (s - (s1 - z)) + (p - z);
-      s = s1;
-      if constexpr (Track) {
-        const double q1 = q + t;
-        double zq = q1 - q;
-        const double et = (q - (q1 - zq)) + (t - zq);
-        const double q2 = q1 + e;
-        zq = q2 - q1;
-        const double ee = (q1 - (q2 - zq)) + (e - zq);
-        q = q2;
-        exactq &= (et == 0.0) & (ee == 0.0);
-      } else {
-        q += t;
-        q += e;
+      p[u] = a[u] * b[u];
+      const double ap = fabs(p[u]);
+      ok &= (ap >= kProdLo && ap < kProdHi) || (p[u] == 0.0 && (a[u] == 0.0 || b[u] == 0.0));
+      v[8 + u] = fma(a[u], b[u], -p[u]);
+    }
+    double l1[4], l2[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) l1[i] = tsum(p[2 * i], p[2 * i + 1], v[i]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) l2[i] = tsum(l1[2 * i], l1[2 * i + 1], v[4 + i]);
+    const double sb = tsum(l2[0], l2[1], v[6]);
+    if (j0 == 0) {
+      s = sb;
+      v[7] = 0.0;
+    } else {
+      s = tsum(s, sb, v[7]);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) m += fabs(v[u]);
+#pragma unroll
+    for (int width = 8; width >= 1; width >>= 1) {
+#pragma unroll
+      for (int i = 0; i < width; ++i) {
+        if constexpr (Track) {
+          double err;
+          v[i] = tsum(v[i], v[i + width], err);
+          exactq &= (err == 0.0);
+        } else {
+          v[i] = v[i] + v[i + width];
+        }
       }
-      m += fabs(t) + fabs(e);
+    }
+    if constexpr (Track) {
+      double err;
+      q = tsum(q, v[0], err);
+      exactq &= (err == 0.0);
+    } else {
+      q += v[0];
     }
   }
   if (Track && ok && exactq) {  // q is the exact sum of the error terms
     y = s + q;
     return true;
   }
-  const double k = 2.0 * w + 2.0;
+  const double k = 16.0 * nb + 2.0;  // sixteen error terms per batch
   const double E = (m * (k * 0x1p-53)) * (1.0 + 0x1p-28) + k * 0x1p-1074;
   const double y0 = s + q;
   if (ok && m == 0.0) {  // every error term is 0: the sum is s exactly (+0 for a zero row)

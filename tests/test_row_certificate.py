@@ -14,33 +14,62 @@ import pytest
 K_LO, K_HI = 2.0 ** -968, 2.0 ** 990
 
 
+def tsum(x, y):
+    """twosum: (RN(x + y), its exact error)"""
+    r = x + y
+    z = r - x
+    return r, (x - (r - z)) + (y - z)
+
+
 def certify(a, x, track=False):
-    """(certified, y) by the kernel's steps for one row: terms a[j] * x[j];
+    """(certified, y) by the kernel's steps for one row: terms a[j] * x[j] in
+    batches of eight (zero-padded), each summed by a pairwise twosum tree into
+    the running sum s, the sixteen error terms of a batch pairwise into q;
     track: also accept a correction sum q that was accumulated exactly."""
     s = q = m = 0.0
     ok = True
     exactq = True
-    for aj, xj in zip(a, x):
-        p = aj * xj
-        ok &= (K_LO <= abs(p) < K_HI) or (p == 0.0 and (aj == 0.0 or xj == 0.0))
-        e = float(F(aj) * F(xj) - F(p)) if math.isfinite(p) else 0.0   # fma(a, x, -p)
-        s1 = s + p
-        z = s1 - s
-        t = (s - (s1 - z)) + (p - z)
-        s = s1
-        if track:
-            for term in (t, e):
-                q1 = q + term
-                zq = q1 - q
-                exactq &= ((q - (q1 - zq)) + (term - zq)) == 0.0
-                q = q1
+    nb = 0
+    for j0 in range(0, len(a), 8):
+        av = list(a[j0:j0 + 8]) + [0.0] * (8 - len(a[j0:j0 + 8]))
+        xv = list(x[j0:j0 + 8]) + [0.0] * (8 - len(x[j0:j0 + 8]))
+        p = [aj * xj for aj, xj in zip(av, xv)]
+        v = [0.0] * 16
+        for u in range(8):
+            ok &= (K_LO <= abs(p[u]) < K_HI) or (p[u] == 0.0 and (av[u] == 0.0 or xv[u] == 0.0))
+            # fma(a, x, -p)
+            v[8 + u] = float(F(av[u]) * F(xv[u]) - F(p[u])) if math.isfinite(p[u]) else 0.0
+        l1 = [0.0] * 4
+        for i in range(4):
+            l1[i], v[i] = tsum(p[2 * i], p[2 * i + 1])
+        l2 = [0.0] * 2
+        for i in range(2):
+            l2[i], v[4 + i] = tsum(l1[2 * i], l1[2 * i + 1])
+        sb, v[6] = tsum(l2[0], l2[1])
+        if j0 == 0:
+            s, v[7] = sb, 0.0
         else:
-            q += t
-            q += e
-        m += abs(t) + abs(e)
+            s, v[7] = tsum(s, sb)
+        for u in range(16):
+            m += abs(v[u])
+        width = 8
+        while width >= 1:
+            for i in range(width):
+                if track:
+                    v[i], err = tsum(v[i], v[i + width])
+                    exactq &= err == 0.0
+                else:
+                    v[i] = v[i] + v[i + width]
+            width //= 2
+        if track:
+            q, err = tsum(q, v[0])
+            exactq &= err == 0.0
+        else:
+            q += v[0]
+        nb += 1
     if track and ok and exactq:
         return True, s + q
-    k = 2.0 * len(a) + 2.0
+    k = 16.0 * nb + 2.0
     E = (m * (k * 2.0 ** -53)) * (1.0 + 2.0 ** -28) + k * 2.0 ** -1074
     y0 = s + q
     if ok and m == 0.0:
