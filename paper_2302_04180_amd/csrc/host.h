@@ -54,6 +54,11 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Single solves always fit the second rule (grid <= 65535, L <= 1024, N <= 8);
 // the batched solver and the server check it per system (records = tiles).
 constexpr int64_t kMaxPerGroup = int64_t(1) << 29;
+// Solves of at most this many rows with the automatic launch shape run in one
+// workgroup (standard and PCG loops, exact and plain dots): measured faster up
+// to 512 rows and slower from 1,728 on, where one CU's share of the exact rows
+// and dots outweighs the launches it saves
+constexpr int64_t kOneGroupRows = 1024;
 constexpr int64_t kCarryChunks = (int64_t(1) << 31) - 1;
 inline bool records_fit(int64_t records, int64_t lanes, int fpe) {
   return records * (lanes * (int64_t)fpe + 1) <= kCarryChunks;

@@ -24,6 +24,8 @@ struct Kern {
   static rpk_status resid(int G, int B, hipStream_t s, Csr A, Vecs V, Red red);
   // one phase of an iteration (standard: 0..4, pipelined: 0..3)
   static rpk_status phase(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red red);
+  // up to `iters` iterations in one workgroup of B threads (standard and PCG)
+  static rpk_status one(int variant, int B, hipStream_t s, Csr A, Vecs V, Red red, int iters);
 };
 
 // Batched launchers: G = workgroups of the tile-walking kernels, Gf = workgroups

@@ -117,6 +117,18 @@ rpk_status Kern<N>::phase(int variant, int ph, int G, int B, hipStream_t s, Csr 
 }
 
 template <int N>
+rpk_status Kern<N>::one(int variant, int B, hipStream_t s, Csr A, Vecs V, Red red, int iters) {
+  const size_t sh = shm_bytes(N, 2, true, B);
+  if (variant == RPK_STD)
+    return A.unif ? launch(k_std_one<N, true>, 1, B, sh, s, A, V, red, iters)
+                  : launch(k_std_one<N, false>, 1, B, sh, s, A, V, red, iters);
+  if (variant == RPK_PCG)
+    return A.unif ? launch(k_pcg_one<N, true>, 1, B, sh, s, A, V, red, iters)
+                  : launch(k_pcg_one<N, false>, 1, B, sh, s, A, V, red, iters);
+  return RPK_ERR_ARG;
+}
+
+template <int N>
 rpk_status KernB<N>::setup(int Gf, hipStream_t s, Batch b, double tol, int maxit, int variant) {
   RET_IF(launch(kb_setup<N>, Gf, 256, 0, s, b, tol, maxit, variant));
   if (variant == RPK_PIPELINED) return launch(kb_zero_pipe<N>, Gf, 1024, 0, s, b);

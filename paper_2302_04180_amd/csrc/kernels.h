@@ -959,6 +959,60 @@ __device__ __forceinline__ void block_finalize_last(const Shm<N>& s, const Red& 
   block_finalize<N, K, true>(s, red, slot0);
 }
 
+// The only workgroup of a reduction (G = 1): round its K dots into
+// s.res[0..K-1] (their flags into s.misc[1..K]) in LDS, with no accumulator in
+// device memory.  The same bits as block_publish followed by
+// block_finalize_last: an exact dot is the same integer (the window sums added
+// to this workgroup's long accumulator instead of the global one) rounded
+// once, a plain one the workgroup's sum plus zero.  Exact and plain dots.
+template <int N, int K>
+__device__ __forceinline__ void block_reduce_local(Dot<N> (&d)[K], const Shm<N>& s) {
+  static_assert(N != LW8, "lightweight records are merged through the partials");
+  const int tid = threadIdx.x;
+  if constexpr (N > 0) {
+    const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
+    int top[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double mx = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) mx = fmax(mx, fabs(d[j].f.c[k]));
+      top[j] = (mx != 0.0) ? digits3_top(mx) : -1;
+    }
+    block_max_k<N, K>(top, s);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (top[j] < 0) continue;
+      const long long cs = wave_window(d[j].f, top[j] - (WIN - 1), s, s.sa + (size_t)j * SA_D, &s.flag[j]);
+      if (lane < WIN) s.wsum[(w * K + j) * WIN + lane] = cs;
+    }
+    __syncthreads();
+    if (tid < K * WIN) {  // one (dot, digit) per thread: no two write one digit
+      const int j = tid / WIN, k = tid % WIN;
+      int tj = top[0];
+#pragma unroll
+      for (int jj = 1; jj < K; ++jj)
+        if (jj == j) tj = top[jj];
+      if (tj >= 0) {
+        long long v = 0;
+        for (int i = 0; i < nw; ++i) v += s.wsum[(i * K + j) * WIN + k];
+        const int g = tj - (WIN - 1) + k;
+        if (v != 0 && g >= 0 && g < SA_D) s.sa[(size_t)j * SA_D + g] += v;
+      }
+    }
+    if (tid < K) s.misc[1 + tid] = s.flag[tid] & F_NONFINITE;
+    __syncthreads();
+    block_round_sa<N, K>(s);
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const double t = plain_block_sum(d[j].s, s.pbuf);
+      if (tid == 0) s.res[j] = 0.0 + t;
+    }
+    __syncthreads();
+  }
+}
+
 // Zero the exact accumulators and flags of slots slot0..slot0+K-1 (one
 // workgroup; device-scope stores, so the atomics of a later kernel see them).
 // Plain slots need nothing: every publication overwrites them.

@@ -7,6 +7,7 @@
 // the stop are no-ops, so the result does not depend on the chunk size.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -33,9 +34,11 @@ namespace {
 
 struct Cfg {
   int block, grid, fpe, graph;
+  int one;  // solve: every iteration in one workgroup (k_std_one / k_pcg_one)
 };
 
 rpk_status resolve(const rpk_launch* L, int64_t n, Cfg* c) {
+  c->one = 0;
   c->block = (L && L->block) ? L->block : 512;
   c->fpe = (L && L->fpe) ? L->fpe : 3;
   c->graph = L ? L->graph : 0;
@@ -118,6 +121,12 @@ template <int N>
 struct PhaseF {
   static rpk_status call(int variant, int ph, int G, int B, hipStream_t s, Csr A, Vecs V, Red r) {
     return Kern<N>::phase(variant, ph, G, B, s, A, V, r);
+  }
+};
+template <int N>
+struct OneF {
+  static rpk_status call(int variant, int B, hipStream_t s, Csr A, Vecs V, Red r, int iters) {
+    return Kern<N>::one(variant, B, s, A, V, r, iters);
   }
 };
 
@@ -469,11 +478,26 @@ rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t d
   return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, Ac, x, y);
 }
 
+// Launch shape of a solve: that of the streaming kernels, except that a small
+// standard or PCG solve with the automatic shape and exact or plain dots runs
+// all its iterations in one workgroup of 1024 threads and one launch (up to
+// kOneGroupRows rows, where that beats five or three launches per iteration).
+static rpk_status solve_shape(const rpk_matrix* A, const rpk_opts* o, Cfg* c) {
+  RET_IF(resolve(&o->launch, A->n, c));
+  if (o->launch.grid == 0 && o->launch.block == 0 && A->n <= kOneGroupRows &&
+      (o->variant == RPK_STD || o->variant == RPK_PCG) && o->dots != RPK_DOT_FPE) {
+    c->grid = 1;
+    c->block = 1024;
+    c->one = 1;
+  }
+  return RPK_OK;
+}
+
 rpk_status rpk_solve_workspace_bytes(const rpk_matrix* A, const rpk_opts* o, size_t* bytes) {
   if (!A || !o || !bytes) return RPK_ERR_ARG;
   if (o->variant != RPK_STD && o->variant != RPK_PIPELINED && o->variant != RPK_PCG) return RPK_ERR_ARG;
   Cfg c;
-  RET_IF(resolve(&o->launch, A->n, &c));
+  RET_IF(solve_shape(A, o, &c));
   *bytes = layout(c.grid, A->n, nvec_of(o->variant)).total;
   return RPK_OK;
 }
@@ -509,7 +533,7 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
   if (o->dots != RPK_DOT_EXACT && o->dots != RPK_DOT_PLAIN && o->dots != RPK_DOT_FPE) return RPK_ERR_ARG;
   if (o->maxit < 0 || !(o->tol >= 0.0)) return RPK_ERR_ARG;
   Cfg c;
-  RET_IF(resolve(&o->launch, A->n, &c));
+  RET_IF(solve_shape(A, o, &c));
   const Layout l = layout(c.grid, A->n, nvec_of(o->variant));
   if (ws_bytes < l.total) return RPK_ERR_ARG;
   info->used.block = c.block;
@@ -603,6 +627,12 @@ rpk_status rpk_solve(const rpk_matrix* A, const double* b, double* x, const rpk_
           info->phase_launches[ph] += 1;
         }
         launched += 1;
+      } else if (c.one) {
+        // the kernel stops itself at the stop test, at maxit at the latest
+        const int iters = o->maxit < INT_MAX ? o->maxit + 1 : INT_MAX;
+        st = by_dot<OneF>(N, variant, B, s, Ac, V, red, iters);
+        if (st != RPK_OK) break;
+        launched += iters;
       } else if (use_graph) {
         const std::vector<uint64_t> key{(uint64_t)(uintptr_t)A, (uint64_t)(uintptr_t)b, (uint64_t)(uintptr_t)x,
                                         (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)o->hist,

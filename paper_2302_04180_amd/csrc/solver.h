@@ -314,10 +314,18 @@ __device__ __forceinline__ void finish_step(const Shm<N>& s, const Vecs& V) {
 }
 
 // Publish this workgroup's K dot partials; the last workgroup to arrive rounds
-// the dots and takes the scalar step F.
+// the dots and takes the scalar step F.  A workgroup that is the only one
+// (exact and plain dots) rounds them in LDS at once.
 template <int N, int K, int F>
 __device__ __forceinline__ void publish_step(Dot<N> (&d)[K], const Shm<N>& s, const Vecs& V, const Red& red,
                                              int rec) {
+  if constexpr (N != LW8) {
+    if (red.G == 1) {
+      block_reduce_local<N, K>(d, s);
+      if (threadIdx.x == 0) finish_step<N, K, F>(s, V);
+      return;
+    }
+  }
   if (!block_publish_last<N, K>(d, s, red, 0, rec, F & 7)) return;
   block_finalize_last<N, K>(s, red, 0);
   if (threadIdx.x == 0) finish_step<N, K, F>(s, V);
@@ -1335,6 +1343,60 @@ __global__ void __launch_bounds__(1024) k_pcg_S3(Csr A, Vecs V, Red red) {
     if (st->done) return;
     shm_init(s, 2);
     pcg_S3_body<N, Unif, false>(A, V, red, my_rows(A.n), blockIdx.x, s, st->rho, st->iter);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small systems: one workgroup takes every phase of up to `iters` iterations in
+// one launch, the phases separated by workgroup barriers and each reduction
+// point finished at once by that workgroup, the only one to publish (G = 1).
+// A solve whose iterations are bound by launch latency then pays one launch
+// instead of five (PCG: three) per iteration.  The phases are the bodies of the
+// multi-workgroup kernels in the order of the single-solve kernels (PCG: S10
+// of an iteration opens the next one, so that a stop leaves the state a resumed
+// solve continues from), so the values are the same bits.  Stops, with every
+// thread, at the first phase after the state says done.
+// ---------------------------------------------------------------------------
+template <int N, bool Unif>
+__global__ void __launch_bounds__(1024) k_std_one(Csr A, Vecs V, Red red, int iters) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  const Range R{0, A.n};
+  const State* st = V.st;
+  for (int k = 0; k < iters; ++k) {
+    if (st->done) return;
+    std_A_body<false, Unif>(A, V, R, st->beta, st->omega, st->iter > 0);  // S12, S1
+    shm_init(s, 1);  // ends with a barrier: A's stores are seen by every thread
+    std_B_body<N, Unif, false>(A, V, red, R, 0, s);  // S2, S3
+    __syncthreads();
+    if (st->done) return;
+    std_C_body<false, Unif>(A, V, R, st->alpha);  // S4, S5
+    shm_init(s, 2);
+    std_D_body<N, Unif, false>(A, V, red, R, 0, s);  // S6, S7
+    __syncthreads();
+    if (st->done) return;
+    shm_init(s, 2);
+    std_E_body<N, false, Unif>(A, V, red, R, 0, s, st->alpha, st->omega, st->iter);  // S8..S11
+    __syncthreads();
+  }
+}
+
+template <int N, bool Unif>
+__global__ void __launch_bounds__(1024) k_pcg_one(Csr A, Vecs V, Red red, int iters) {
+  extern __shared__ __align__(16) char smem[];
+  Shm<N> s = shm_carve<N>(smem, 2, true);
+  const Range R{0, A.n};
+  const State* st = V.st;
+  for (int k = 0; k < iters; ++k) {
+    if (st->done) return;
+    if (st->iter > 0) pcg_S10_body<Unif>(A, V, R, st->alpha);  // S10 of the iteration before
+    shm_init(s, 1);
+    pcg_S1_body<N, false>(A, V, red, R, 0, s);  // S1, S2
+    __syncthreads();
+    if (st->done) return;
+    shm_init(s, 2);
+    pcg_S3_body<N, Unif, false>(A, V, red, R, 0, s, st->rho, st->iter);  // S3..S9
+    __syncthreads();
   }
 }
 
