@@ -478,14 +478,19 @@ rpk_status rpk_exspmv(const rpk_matrix* A, const double* x, double* y, int32_t d
   return by_fpe<SpmvF>(N, c.grid, c.block, (hipStream_t)stream, Ac, x, y);
 }
 
-// Launch shape of a solve: that of the streaming kernels, except that a small
-// standard or PCG solve with the automatic shape and exact or plain dots runs
-// all its iterations in one workgroup of 1024 threads and one launch (up to
-// kOneGroupRows rows, where that beats five or three launches per iteration).
+// Launch shape of a solve: that of the streaming kernels, except with the
+// automatic shape (block and grid 0) on small systems: a standard or PCG solve
+// with exact or plain dots of up to kOneGroupRows rows runs all its iterations
+// in one workgroup of 1024 threads and one launch, and other solves of fewer
+// than kSmallBlockRows rows take workgroups of 256 threads (twice as many
+// workgroups: latency-bound iterations spread over more CUs).
 static rpk_status solve_shape(const rpk_matrix* A, const rpk_opts* o, Cfg* c) {
-  RET_IF(resolve(&o->launch, A->n, c));
-  if (o->launch.grid == 0 && o->launch.block == 0 && A->n <= kOneGroupRows &&
-      (o->variant == RPK_STD || o->variant == RPK_PCG) && o->dots != RPK_DOT_FPE) {
+  const bool automatic = o->launch.grid == 0 && o->launch.block == 0;
+  rpk_launch L = o->launch;
+  if (automatic && A->n < kSmallBlockRows) L.block = 256;
+  RET_IF(resolve(&L, A->n, c));
+  if (automatic && A->n <= kOneGroupRows && (o->variant == RPK_STD || o->variant == RPK_PCG) &&
+      o->dots != RPK_DOT_FPE) {
     c->grid = 1;
     c->block = 1024;
     c->one = 1;

@@ -50,7 +50,7 @@ def check_pair(M, b, tol, maxit, variant, dots=rpk.EXACT, one=True):
     if one and dots != rpk.FPE:
         assert i1["used"]["grid"] == 1 and i1["used"]["block"] == 1024
     else:
-        assert i1["used"]["block"] == 512
+        assert i1["used"]["block"] == 256  # fewer than 65536 rows: 256-thread workgroups
     assert i2["used"]["block"] == 512
     if dots == rpk.PLAIN:
         assert i1["status"] == i2["status"] == "OK" and abs(i1["iters"] - i2["iters"]) <= 3
