@@ -142,3 +142,22 @@ def test_size_limit(variant, vname):
         M = rpk.Matrix(*A)
         say("size", n, vname, "one workgroup" if one else "many")
         check_pair(M, rhs(M, n, 8), 1e-10, 300, variant, one=one)
+
+
+@pytest.mark.parametrize("variant,vname", LOOPS)
+def test_timing_and_graph_settings(variant, vname):
+    """Timing mode launches the phase kernels one by one (on one workgroup of 1024
+    threads here); a graph setting is ignored by the one-launch path.  Same bits."""
+    A = inputs.poisson7(10)
+    M = rpk.Matrix(*A)
+    b = rhs(M, 1000, 12)
+    x0, i0 = rpk.solve(M, b, tol=1e-10, maxit=300, variant=variant, record=True)
+    assert i0["used"]["grid"] == 1 and i0["status"] == "OK"
+    for kw in ({"timing": True}, {"graph": -1}, {"graph": 5}):
+        x1, i1 = rpk.solve(M, b, tol=1e-10, maxit=300, variant=variant, record=True, **kw)
+        say(vname, kw, i1["used"], i1["iters"])
+        assert i1["used"]["grid"] == 1 and i1["used"]["block"] == 1024
+        assert i1["iters"] == i0["iters"] and same(i1["tau"], i0["tau"]) and same(i1["true_res"], i0["true_res"])
+        assert same(H(i1["hist"]), H(i0["hist"])) and same(H(x1), H(x0))
+        if kw.get("timing"):
+            assert sum(i1["phase_launches"]) > 0
