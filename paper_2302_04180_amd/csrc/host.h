@@ -63,6 +63,8 @@ constexpr int64_t kOneGroupRows = 1024;
 // threads instead of 512: measured 3-12 % faster from 1,728 to 32,768 rows
 // (7-point Poisson, all three loops), slower from 110,592 on
 constexpr int64_t kSmallBlockRows = 65536;
+// Largest automatic chunk of iterations between two looks at a solve's state
+constexpr int kMaxChunk = 64;
 constexpr int64_t kCarryChunks = (int64_t(1) << 31) - 1;
 inline bool records_fit(int64_t records, int64_t lanes, int fpe) {
   return records * (lanes * (int64_t)fpe + 1) <= kCarryChunks;
