@@ -536,7 +536,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched, serving and e-type legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+        print("bench.py measures one GPU only (the library has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
