@@ -90,7 +90,7 @@ typedef enum { RPK_DOT_EXACT = 0, RPK_DOT_PLAIN = 1, RPK_DOT_FPE = 2 } rpk_dotmo
  *     fpe 8 allows 4.1M tiles, tile 4096 with the defaults any n < 2^31).
  * Within the budget no digit can overflow, whatever the data.
  * Small solves (block and grid both 0): a standard or PCG rpk_solve of at most
- * 1024 rows with exact or plain dots runs every iteration in one workgroup of
+ * 512 rows with exact or plain dots runs every iteration in one workgroup of
  * 1024 threads and one kernel launch (graph is then unused; info->used reports
  * grid 1, block 1024); other solves of fewer than 65536 rows use workgroups of
  * 256 threads.  Exact results are the same bits either way. */

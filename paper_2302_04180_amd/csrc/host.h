@@ -55,10 +55,11 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // the batched solver and the server check it per system (records = tiles).
 constexpr int64_t kMaxPerGroup = int64_t(1) << 29;
 // Solves of at most this many rows with the automatic launch shape run in one
-// workgroup (standard and PCG loops, exact and plain dots): measured faster up
-// to 512 rows and slower from 1,728 on, where one CU's share of the exact rows
-// and dots outweighs the launches it saves
-constexpr int64_t kOneGroupRows = 1024;
+// workgroup (standard and PCG loops, exact and plain dots): with exact dots
+// measured faster at 512 rows and slower from 1,000 on, where one CU's share of
+// the exact rows and dots outweighs the launches it saves (the pipelined loop
+// ran slower in one workgroup already at 512 rows)
+constexpr int64_t kOneGroupRows = 512;
 // Solves of fewer rows with the automatic launch shape use workgroups of 256
 // threads instead of 512: measured 3-12 % faster from 1,728 to 32,768 rows
 // (7-point Poisson, all three loops), slower from 110,592 on
