@@ -132,9 +132,9 @@ struct PhaseF {
 // on the stop instead of overshooting it; twice the last chunk when there is no
 // rate to go by; 1..kMaxChunk and not past maxit.  A surplus iteration costs
 // launches that return at once (about 11 us on a small system), a look a host
-// round trip (about 20 us); simulated on the residual histories of 7-point
-// Poisson solves from 12^3 to 128^3 (standard and PCG) this costs 40 % of the
-// doubling chunks it replaced.
+// round trip (20-45 us); simulated on the residual histories of 7-point
+// Poisson solves from 12^3 to 128^3 (standard and PCG) this costs about half of
+// what the doubling chunks it replaced did.
 int next_chunk(const State& h, int look_iter, double look_rel, int prev) {
   const double rel = h.tau / h.tau0;
   int c = 2 * prev;
